@@ -1,0 +1,211 @@
+/*
+ * libiat -- batched classical trajectories of one Paul-trapped ion plus one atom on
+ * AMD Instinct MI355X (gfx950).  C ABI: plain structs, pointers and sizes.
+ *
+ * Model (the paper's Eq. (1) and the model paragraph after it): Newton's equations for
+ * the 12 positions and velocities of an ion (mass m_i) in the time-dependent trap
+ *   U_trap = sum_k (a_k + 2 q_k cos(Omega t + phase0)) m_i Omega^2 r_{i,k}^2 / 8
+ * interacting with an atom (mass m_a) through V(r) = C8/r^8 - C4/r^4, C4 = alpha/2.
+ * C8 is fixed by the well depth De: C8 = C4^2/(4 De), so V(r_m) = -De at
+ * r_m = (C4/(2 De))^(1/4).  Integrated by the adaptive Dormand-Prince 5(4) pair the paper
+ * cites.  Head-on start (head-on-run paragraph): ion at rest at the trap centre, atom on the
+ * sphere of radius r0 moving radially inward with E = m_a v0^2 / 2.  A trajectory ends when
+ * the ion-atom separation crosses r0 outward, or at t_max.
+ *
+ * Units: every physical input and output is in atomic units (a0, m_e, E_h, hbar/E_h);
+ * angles in radians.  Integration runs internally in length a0 and time tau = Omega t;
+ * rtol/atol apply to that internal state (positions in a0, velocities in a0 per unit tau)
+ * and h0/hmax/hmin are in units of tau.
+ *
+ * Memory: pointers are DEVICE pointers unless documented as host.  Output arrays are
+ * caller-allocated, length n, structure-of-arrays.  y_final and y0 are 12 x n,
+ * component-major (element k of trajectory j at [k*n + j]), component order
+ * r_atom(3), r_ion(3), v_atom(3), v_ion(3).
+ * Streams: `stream` is a hipStream_t passed as void*; every call enqueues work on it and
+ * returns without synchronising.  NULL means the default stream.
+ * Errors: 0 = OK, IAT_EINVAL = bad argument (nothing enqueued), IAT_EHIP = HIP runtime
+ * error while enqueueing, IAT_EWORKSPACE = workspace too small, IAT_ENOTSUP = unsupported
+ * option.  iat_last_error() returns a thread-local message for the last nonzero return.
+ * Numerical trouble in a trajectory is never an error return: it sets status bits.
+ */
+#ifndef IAT_H
+#define IAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IAT_EINVAL (-1)
+#define IAT_EHIP (-2)
+#define IAT_EWORKSPACE (-3)
+#define IAT_ENOTSUP (-4)
+
+/* per-trajectory status bits */
+#define IAT_ST_COMPLEX      (1u << 0)  /* >= 2 bounces, or still bound at t_max (Fig. 1 text:
+                                          a direct collision is a single bounce)            */
+#define IAT_ST_BOUND_SEEN   (1u << 1)  /* relative energy < 0 at some accepted step (the
+                                          negative-energy bound state of the Eq. (2) text)  */
+#define IAT_ST_EXITED       (1u << 2)  /* separation crossed r0 outward: the normal end     */
+#define IAT_ST_TMAX         (1u << 8)  /* reached t_max                                     */
+#define IAT_ST_H_UNDERFLOW  (1u << 9)  /* step size fell below hmin                         */
+#define IAT_ST_NONFINITE    (1u << 10) /* non-finite state                                  */
+#define IAT_ST_MAX_STEPS    (1u << 11) /* accepted-step cap reached                         */
+#define IAT_ST_R_UNDERFLOW  (1u << 12) /* separation below 0.1 r_m (integration broken)     */
+#define IAT_ST_WARN_R0      (1u << 13) /* start violates 10|V(r0)| < E (head-on-run text)   */
+#define IAT_ST_ADJ_SKIPPED  (1u << 14) /* gradient not computed (step cap); grads are NaN   */
+
+#define IAT_MAX_SPECIES 8
+#define IAT_DEFAULT_MAX_STEPS 20000000LL  /* used when iat_system.max_steps == 0 */
+
+/* One atomic species: mass (m_e) and C4 = alpha/2 (a.u.). */
+typedef struct {
+    double m_atom;
+    double C4;
+} iat_species;
+
+/* Trap, per-batch defaults and integrator settings (host struct, copied at call time). */
+typedef struct {
+    double m_ion;             /* m_e                                                    */
+    double omega_rf;          /* Omega, 1/(a.u. time)                                   */
+    double a_x, q_x;          /* default Mathieu parameters of the x axis               */
+    double a_ratio[3];        /* a_k = a_x * a_ratio[k]; ring trap (1, 1, -2)           */
+    double q_ratio[3];        /* q_k = q_x * q_ratio[k]; ring trap (1, 1, -2)           */
+    double E;                 /* default collision energy, E_h                          */
+    double De;                /* default well depth, E_h                                */
+    double phase0;            /* default RF phase Omega t0 at t = 0                     */
+    int32_t species;          /* default species index                                  */
+    int32_t reserved0;
+    double r0;                /* start/exit sphere radius, a0                           */
+    double t_max;             /* a.u. time                                              */
+    double rtol, atol;        /* error tolerances on the internal state                 */
+    double h0, hmax, hmin;    /* tau units; 0 -> 2pi*1e-3, 2pi/8, 1e-6*h0               */
+    double r_bounce_over_rm;  /* bounce = periapsis inside this many r_m; 0 -> 1        */
+    int64_t max_steps;        /* accepted-step cap; 0 -> IAT_DEFAULT_MAX_STEPS          */
+} iat_system;
+
+enum { IAT_GEN_ARRAYS = 0, IAT_GEN_GRID = 1, IAT_GEN_SWEEP = 2 };
+
+/* How trajectory ids map to parameters.
+ *  GRID : cell-centred (theta, phi) grid on the octant (Fig. 1),
+ *         theta_j = (j+1/2)(pi/2)/n_theta, phi_k = (k+1/2)(pi/2)/n_phi, id = j*n_phi + k;
+ *         E, q_x, De, phase0, species from iat_system.
+ *  SWEEP: Philox4x64-10 (Salmon et al., SC'11) blocks (id, 0, 0, 0) and (id, 1, 0, 0) under
+ *         key (seed, 0) give uniforms u0..u7 = (x >> 11) 2^-53; cos(theta) = 1 - 2 u0,
+ *         phi = 2 pi u1, phase0 = 2 pi u2 (random RF phase of the Fig. 4 runs);
+ *         E = E_lo (E_hi/E_lo)^u3 or a list, q_x = q_lo + (q_hi - q_lo) u4 or a list,
+ *         De = De_lo (De_hi/De_lo)^u5 or a list.  Lists are indexed by the mixed-radix
+ *         digits of cell = id mod (n_species * n_E' * n_q' * n_De') with species slowest
+ *         and De fastest (n' = max(n, 1)).
+ *  ARRAYS: per-trajectory device arrays in iat_batch (NULL entries take the defaults). */
+typedef struct {
+    int32_t kind;
+    int32_t n_theta, n_phi;
+    int32_t n_species;
+    int32_t species[IAT_MAX_SPECIES];
+    int32_t n_E, n_q, n_De;
+    int32_t reserved0;
+    double E[8], q[8], De[8];
+    double E_lo, E_hi, q_lo, q_hi, De_lo, De_hi;
+    uint64_t seed;
+    int64_t id0;              /* global id of this call's first trajectory (streaming)  */
+} iat_gen;
+
+typedef struct {
+    int64_t n;                               /* number of trajectories (>= 0)         */
+    const double *theta, *phi, *E, *q_x, *De, *phase0;  /* ARRAYS mode, device, or NULL */
+    const int32_t* species;                  /* ARRAYS mode, device, or NULL          */
+    const double* y0;                        /* 12 x n start states (a.u.), or NULL:
+                                                overrides the head-on start (any mode) */
+    iat_gen gen;
+} iat_batch;
+
+/* Outputs (device, length n, caller-allocated).  Required: angle, q_transfer, dE_ion,
+ * t_dwell, n_bounce, status.  Optional (NULL = not written): the rest.
+ *   angle      = atan2(|v_i x v_f|, v_i . v_f) of the atom's initial/final velocity,
+ *                i.e. arccos(v_i.v_f/(v_i v_f)) (Fig. 1 caption)
+ *   q_transfer = m_a |v_f - v_i| (Fig. 1 caption)
+ *   dE_ion     = E_ion(t_f) - E_ion(0), E_ion = ion kinetic + trap terms of Eq. (1)
+ *   t_dwell    = t_f; t_bounce_first/last = time of the first/last bounce (0 if none)  */
+typedef struct {
+    double *angle, *q_transfer, *dE_ion, *t_dwell, *t_bounce_first, *t_bounce_last;
+    int32_t* n_bounce;
+    uint32_t* status;
+    int64_t *n_accept, *n_reject, *n_rhs;
+    double* y_final;
+} iat_obs;
+
+enum { IAT_KERNEL_PLAIN = 1, IAT_KERNEL_PERSISTENT = 2 };
+
+/* Launch shape.  kernel: PLAIN = one lane per trajectory, one launch per batch;
+ * PERSISTENT = resident grid whose lanes refill from a device work queue.
+ * Zero fields take defaults.  stats, if not NULL, is a device uint64[8] to which the
+ * call ADDS: [0] RHS evaluations, [1] accepted steps, [2] rejected steps,
+ * [3] trajectories finished, [4] issued lane-steps (wave iterations x 64),
+ * [5] useful lane-steps (attempted steps). */
+typedef struct {
+    int32_t kernel;
+    int32_t block;            /* threads per block (multiple of 64, <= 1024)           */
+    int32_t blocks_per_cu;    /* PERSISTENT: resident blocks per CU (0 = occupancy max) */
+    int32_t refill_every;     /* PERSISTENT: attempted steps between refills (>= 1)    */
+    int32_t reserved[4];
+    uint64_t* stats;
+} iat_launch;
+
+/* Integrate a batch (the paper's head-on runs: model paragraph, head-on-run paragraph,
+ * observables of the Fig. 1 caption).  ckpt_ws/ckpt_bytes: adjoint checkpoint workspace
+ * (see iat_adjoint), or NULL/0.  Returns 0 or an error code. */
+int iat_integrate(const iat_system* sys, const iat_species* species /* host */, int n_species,
+                  const iat_batch* batch, const iat_obs* obs, const iat_launch* launch,
+                  void* ckpt_ws, size_t ckpt_bytes, void* stream);
+
+/* Reductions of a batch's outputs (the ensemble quantities of Figs. 3 and 4).
+ * kind IAT_REDUCE_CELLS: per cell c of the SWEEP generator (cell = id mod n_cells), out is
+ *   double[n_cells * 5] = (count, complex count, sum dE_ion, sum dE_ion^2, sum n_bounce).
+ * kind IAT_REDUCE_W0_HIST: per species s, 64 bins of log10(E/W0) over [-3, 3] (clamped),
+ *   W0 from Eq. (2) with omega = (Omega/2) sqrt(a_x + q_x^2/2); out is double[n_species*64*2]
+ *   = (total, complex) counts; then 256 bins of the ion heating
+ *   sign(dE) log10(1 + |dE|/(k_B 1 nK)) over +-log10(1 + 1e8) (clamped): double[256].
+ * Sums are accumulated in a fixed order, so results do not depend on scheduling.
+ * out is device memory that the call ADDS to (zero it first to start). */
+#define IAT_REDUCE_CELLS 1
+#define IAT_REDUCE_W0_HIST 2
+int iat_reduce(const iat_system* sys, const iat_species* species, int n_species,
+               const iat_batch* batch, const iat_obs* obs, int kind, double* out, void* stream);
+
+/* Tangent-linear of the accepted-step map (internal differentiation: the tangent columns
+ * obey the same Runge-Kutta scheme with the primal's step sequence).  Per trajectory:
+ * dobs_dp[15*n] = d(angle, q_transfer, dE_ion)/d(theta, phi, E, q_x, De), laid out
+ * [j*15 + 5*i + p]; ftle[n] = ln(sigma_max(Phi(t_f, 0)))/t_f (per a.u. time), Phi the
+ * 12x12 stability matrix of the internal state; Phi_out[144*n] (row-major per
+ * trajectory, internal units) or NULL.  Head-on GRID/ARRAYS batches only. */
+int iat_integrate_tangent(const iat_system* sys, const iat_species* species, int n_species,
+                          const iat_batch* batch, const iat_obs* obs, double* dobs_dp, double* ftle,
+                          double* Phi_out, const iat_launch* launch, void* stream);
+
+/* Discrete adjoint of the accepted-step map: p_bar[5*n] = (d/dp) sum_k obs_bar[3*j+k] obs_k
+ * for p = (theta, phi, E, q_x, De), using checkpoints (state, time, step) that iat_integrate
+ * stored every 256 accepted steps in ckpt_ws; segments are recomputed in scratch.
+ * Trajectories that did not fit the workspace get NaN and IAT_ST_ADJ_SKIPPED. */
+int iat_adjoint(const iat_system* sys, const iat_species* species, int n_species,
+                const iat_batch* batch, const iat_obs* obs, const double* obs_bar, double* p_bar,
+                const void* ckpt_ws, size_t ckpt_bytes, void* scratch, size_t scratch_bytes,
+                const iat_launch* launch, void* stream);
+
+#define IAT_WS_CKPT 1
+#define IAT_WS_ADJ_SCRATCH 2
+/* Bytes needed for a workspace (host query). */
+int iat_workspace_bytes(int which, const iat_system* sys, const iat_batch* batch, size_t* bytes);
+
+const char* iat_last_error(void);
+/* Library version string. */
+const char* iat_version(void);
+/* Free per-device library state (queue counters); safe to call at exit. */
+void iat_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

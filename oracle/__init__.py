@@ -16,6 +16,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
+# Round-off twin: the same sources compiled with FMA contraction.  Its spread from the main
+# build measures how strongly a trajectory amplifies round-off (its conditioning).
+TWIN_PATH = os.path.join(HERE, "liboracle_twin.so")
 SOURCES = ["iat_oracle.c", "iat_oracle_tangent.c"]
 
 COMPLEX, BOUND_SEEN, EXITED = 1 << 0, 1 << 1, 1 << 2
@@ -43,14 +46,15 @@ class _Sweep(ctypes.Structure):
 
 
 def build(force: bool = False) -> str:
-    """Compile liboracle.so with gcc (plain IEEE FP64: no fast-math, no FMA contraction)."""
+    """Compile liboracle.so with gcc (plain IEEE FP64: no fast-math, no FMA contraction) and
+    its round-off twin liboracle_twin.so (identical sources, FMA contraction on)."""
     srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
-    if not force and os.path.exists(LIB_PATH):
+    if not force and os.path.exists(LIB_PATH) and os.path.exists(TWIN_PATH):
         return LIB_PATH
-    cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-o", LIB_PATH + ".tmp", *srcs, "-lm"]
-    subprocess.check_call(cmd)
-    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    base = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-fno-fast-math"]
+    for path, extra in ((LIB_PATH, ["-ffp-contract=off"]), (TWIN_PATH, ["-mfma", "-ffp-contract=fast"])):
+        subprocess.check_call(base + extra + ["-o", path + ".tmp", *srcs, "-lm"])
+        os.replace(path + ".tmp", path)
     return LIB_PATH
 
 
@@ -188,12 +192,29 @@ def problems_for(workload, ids) -> np.ndarray:
     return out
 
 
-def integrate(problems: np.ndarray, nthreads: int = 0) -> np.ndarray:
+_twin = None
+
+
+def twin_lib():
+    global _twin
+    if _twin is None:
+        if not os.path.exists(TWIN_PATH):
+            build(force=True)
+        T = ctypes.CDLL(TWIN_PATH)
+        T.orc_integrate_batch.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+        _twin = T
+    return _twin
+
+
+def integrate(problems: np.ndarray, nthreads: int = 0, twin: bool = False) -> np.ndarray:
+    """Integrate a batch of orc_problem records (OpenMP over trajectories).  twin=True runs the
+    round-off twin build instead."""
     problems = np.ascontiguousarray(problems, dtype=PROBLEM)
     res = np.zeros(len(problems), dtype=RESULT)
     if nthreads <= 0:
         nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    lib().orc_integrate_batch(len(problems), _ptr(problems), _ptr(res), nthreads)
+    L = twin_lib() if twin else lib()
+    L.orc_integrate_batch(len(problems), _ptr(problems), _ptr(res), nthreads)
     return res
 
 

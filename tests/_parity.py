@@ -1,0 +1,168 @@
+"""Comparison of library outputs with the CPU oracle, trajectory by trajectory and in ensemble.
+
+Per-trajectory bar (trajectories with at most one bounce that exit normally in both runs):
+1e-8 relative on the final state and the observables, identical bounce count and status.
+The final state is compared at a common time: the exit time is itself a computed quantity, and
+the ion's micromotion makes its state swing on the RF time scale, so the library's state is first
+carried to the oracle's exit time with its time derivative (first order in the exit-time
+difference, which is itself held to the bar).  The ion energy change is compared the same way.
+
+Where a direct trajectory amplifies round-off so much that the result is not unique to 1e-8 (a
+deep well at low collision energy, or a start near the boundary of the regular region), the
+oracle itself shows it: five round-off probes (the oracle's twin build with FMA contraction, and
+the oracle with the atom's start position moved by one ulp in four sign patterns) spread by s.
+Such a trajectory is held to max(1e-8, 10 s) instead; with s <= 1e-9 the bar is exactly 1e-8.
+
+Ensemble bar (all other trajectories, which are chaotic): complex probability, mean ion heating
+and the bounce-count histogram, each within 3 standard errors.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import oracle
+
+REL = 1e-8
+BOUNCE_BINS = [(0, 0), (1, 1), (2, 2), (3, 4), (5, 8), (9, 16), (17, 10 ** 9)]
+
+
+def to_numpy(out: dict) -> dict:
+    return {k: v.detach().cpu().numpy() for k, v in out.items()}
+
+
+def _rel(a, b, floor=0.0):
+    return abs(a - b) / max(abs(b), floor)
+
+
+def field_errors(p, r, g, i):
+    """Relative differences of trajectory i between the oracle record r and the outputs g
+    (dict of arrays): exit time, angle, momentum transfer, the four 3-vector blocks of the final
+    state carried to the oracle's exit time, and the ion energy change at that time."""
+    e = {k: _rel(g[k][i], r[k]) for k in ("t_dwell", "angle", "q_transfer")}
+    if "y_final" in g:
+        yg = np.asarray(g["y_final"][:, i], dtype=np.float64)
+        tg, tr = float(g["t_dwell"][i]), float(r["t_dwell"])
+        ya = yg + oracle.rhs_au(p, tg, yg) * (tr - tg)
+        yr = r["y_final"]
+        for b in range(4):
+            sl = slice(3 * b, 3 * b + 3)
+            e[f"y_final[{b}]"] = np.linalg.norm(ya[sl] - yr[sl]) / np.linalg.norm(yr[sl])
+        dEa = oracle.ion_energy(p, ya, tr) - oracle.ion_energy(p, p["y0"], 0.0)
+        e["dE_ion(aligned)"] = _rel(dEa, r["dE_ion"])
+    return e
+
+
+def as_outputs(res):
+    """oracle result records -> the dict-of-arrays layout of the library outputs"""
+    g = {k: res[k] for k in ("angle", "q_transfer", "dE_ion", "t_dwell", "n_bounce", "status", "n_accept",
+                             "n_reject", "n_rhs")}
+    g["y_final"] = np.ascontiguousarray(res["y_final"].T)
+    return g
+
+
+def per_trajectory_mismatches(problems, ref, got, idx, rel=REL, check_counts=True, spread=None):
+    """(index, field, value) triples breaking the per-trajectory bar: rel, or with the per-index
+    round-off spread s of the oracle, max(rel, 10 s)."""
+    bad = []
+    for j, i in enumerate(idx):
+        p = problems[i]
+        r = ref[i]
+        if got["n_bounce"][i] != r["n_bounce"]:
+            bad.append((i, "n_bounce", (got["n_bounce"][i], r["n_bounce"])))
+            continue
+        if int(got["status"][i]) & 0xFFFF != int(r["status"]):
+            bad.append((i, "status", (hex(int(got["status"][i])), hex(int(r["status"])))))
+        if check_counts:
+            for k in ("n_accept", "n_reject", "n_rhs"):
+                if k in got and got[k][i] != r[k]:
+                    bad.append((i, k, (got[k][i], r[k])))
+        bar = rel if spread is None else max(rel, 10.0 * spread[j])
+        for k, e in field_errors(p, r, got, i).items():
+            if not e <= bar:
+                bad.append((i, k, e))
+    return bad
+
+
+PROBE_SIGNS = (np.array([1.0, -1.0, 1.0]), np.array([-1.0, 1.0, 1.0]), np.array([1.0, 1.0, -1.0]),
+               np.array([-1.0, -1.0, -1.0]))
+
+
+def _direct(res, i):
+    return res[i]["n_bounce"] <= 1 and (res[i]["status"] & oracle.EXITED) != 0
+
+
+def probe_spread(problems, ref, idx):
+    """Round-off spread s of each trajectory in idx: the worst field difference between the
+    oracle and five round-off probes of it.  inf when a probe is no longer a direct exit."""
+    idx = np.asarray(idx, dtype=np.int64)
+    if len(idx) == 0:
+        return np.zeros(0)
+    sub = np.ascontiguousarray(problems[idx])
+    runs = [oracle.integrate(sub, twin=True)]
+    for sg in PROBE_SIGNS:
+        q = sub.copy()
+        q["y0"][:, 0:3] *= 1.0 + sg * 2.0 ** -52
+        runs.append(oracle.integrate(q))
+    spread = np.zeros(len(idx))
+    for run in runs:
+        g = as_outputs(run)
+        for j, i in enumerate(idx):
+            if not _direct(run, j):
+                spread[j] = np.inf
+            else:
+                spread[j] = max(spread[j], max(field_errors(problems[i], ref[i], g, j).values()))
+    return spread
+
+
+def classify(problems, ref, got):
+    """Split trajectory indices into direct ones (<= 1 bounce and a normal exit in the oracle, in
+    every round-off probe and in the library), with their round-off spread s, and the rest
+    (compared in ensemble).  Returns (direct, spread, rest)."""
+    gs = got["status"].astype(np.int64)
+    one = (ref["n_bounce"] <= 1) & ((ref["status"] & oracle.EXITED) != 0) & (got["n_bounce"] <= 1) & \
+          ((gs & oracle.EXITED) != 0)
+    cand = np.where(one)[0]
+    spread = probe_spread(problems, ref, cand)
+    ok = np.isfinite(spread)
+    rest = np.sort(np.concatenate([np.where(~one)[0], cand[~ok]]))
+    return cand[ok], spread[ok], rest
+
+
+def per_trajectory_bar(spread, rel=REL):
+    return np.maximum(rel, 10.0 * spread)
+
+
+def bounce_hist(nb, status):
+    tmax = (status & oracle.TMAX) != 0
+    h = [np.sum((nb >= lo) & (nb <= hi) & ~tmax) for lo, hi in BOUNCE_BINS]
+    h.append(np.sum(tmax))
+    return np.array(h, dtype=np.float64)
+
+
+def ensemble_mismatches(ref, got, idx, k_se=3.0):
+    """Complex probability, mean heating and bounce histogram of the subset idx, within k_se SE."""
+    idx = np.asarray(idx)
+    bad = []
+    if len(idx) < 2:
+        return bad
+    n = len(idx)
+    cr = (ref["status"][idx] & oracle.COMPLEX) != 0
+    cg = (got["status"][idx].astype(np.int64) & oracle.COMPLEX) != 0
+    p1, p2 = cr.mean(), cg.mean()
+    se = math.sqrt(max(p1 * (1 - p1) + p2 * (1 - p2), 1.0 / n) / n)
+    if abs(p1 - p2) > k_se * se:
+        bad.append(("P(complex)", p1, p2, se))
+    er, eg = ref["dE_ion"][idx], got["dE_ion"][idx]
+    se = math.sqrt((er.var(ddof=1) + eg.var(ddof=1)) / n)
+    if abs(er.mean() - eg.mean()) > k_se * max(se, 1e-300):
+        bad.append(("mean dE_ion", er.mean(), eg.mean(), se))
+    hr = bounce_hist(ref["n_bounce"][idx], ref["status"][idx])
+    hg = bounce_hist(got["n_bounce"][idx], got["status"][idx].astype(np.int64))
+    for j in range(len(hr)):
+        q1, q2 = hr[j] / n, hg[j] / n
+        se = math.sqrt(max(q1 * (1 - q1) + q2 * (1 - q2), 1.0 / n) / n)
+        if abs(q1 - q2) > k_se * se:
+            bad.append((f"bounce bin {j}", q1, q2, se))
+    return bad

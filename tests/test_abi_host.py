@@ -1,0 +1,86 @@
+"""Host-only checks of the C ABI: the library loads, exports what include/iat.h declares, and its
+argument validation rejects bad input before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import workloads as W
+from paper_2509_15117_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "iat.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(iat_\w+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_function():
+    L = _abi.load()
+    declared = header_functions()
+    assert set(declared) == set(_abi.EXPORTS), declared
+    for name in declared:
+        assert hasattr(L, name), name
+    assert b"gfx950" in L.iat_version()
+
+
+def test_struct_layouts_match_header_sizes():
+    # sizes implied by the header's field lists (LP64)
+    assert ctypes.sizeof(_abi.System) == 8 * 21 + 8 + 8
+    assert ctypes.sizeof(_abi.Gen) == 64 + 8 * 30 + 16
+    assert ctypes.sizeof(_abi.Obs) == 12 * 8
+    assert ctypes.sizeof(_abi.Launch) == 32 + 8
+
+
+def _call(system=None, species=None, n_species=None, batch=None, obs=None, launch=None):
+    from paper_2509_15117_amd import api  # noqa: F401  (torch import is fine on CPU)
+    w = W.config1()
+    sysv = system or api.system_struct(w.system)
+    sp = species or api.species_array(w.species())
+    b = batch or api.batch_struct(0, w.gen)
+    o = obs if obs is not None else _abi.Obs()
+    la = launch or _abi.Launch()
+    rc = _abi.load().iat_integrate(ctypes.byref(sysv), sp, 1 if n_species is None else n_species, ctypes.byref(b),
+                                   ctypes.byref(o), ctypes.byref(la), None, 0, None)
+    return rc, _abi.load().iat_last_error().decode()
+
+
+def _obs_dummy():
+    o = _abi.Obs()
+    for k in ("angle", "q_transfer", "dE_ion", "t_dwell", "n_bounce", "status"):
+        setattr(o, k, ctypes.c_void_p(0x1000))  # never dereferenced: n == 0 or rejected first
+    return o
+
+
+def test_validation_rejects_bad_arguments_without_gpu():
+    from paper_2509_15117_amd import api
+    w = W.config1()
+    ok, _ = _call(obs=_obs_dummy())
+    assert ok == 0                                   # n == 0: valid and nothing to do
+    ok, _ = _call(obs=_abi.Obs())
+    assert ok == 0                                   # n == 0 needs no output buffers
+    rc, msg = _call(batch=api.batch_struct(4, w.gen), obs=_abi.Obs())
+    assert rc == _abi.IAT_EINVAL and "obs" in msg
+    s = api.system_struct(w.system)
+    s.rtol = 0.0
+    rc, msg = _call(system=s, obs=_obs_dummy())
+    assert rc == _abi.IAT_EINVAL and "rtol" in msg
+    rc, msg = _call(n_species=0, obs=_obs_dummy())
+    assert rc == _abi.IAT_EINVAL and "n_species" in msg
+    b = api.batch_struct(65, w.gen)                  # 8x8 grid holds 64 ids
+    rc, msg = _call(batch=b, obs=_obs_dummy())
+    assert rc == _abi.IAT_EINVAL and "grid" in msg
+    la = api.launch_struct("plain", block=100)
+    rc, msg = _call(launch=la, obs=_obs_dummy())
+    assert rc == _abi.IAT_EINVAL and "block" in msg
+    g = W.Generator(kind="sweep", species=[0, 7], E_range=(1e-12, 1e-11), q_range=(0.1, 0.2),
+                    De_range=(1e-6, 1e-5))
+    rc, msg = _call(batch=api.batch_struct(0, g), obs=_obs_dummy())
+    assert rc == _abi.IAT_EINVAL and "species" in msg
+    s = api.system_struct(w.system)
+    s.hmax = 1.0                                     # > pi/4: beyond an eighth of the RF period
+    rc, msg = _call(system=s, obs=_obs_dummy())
+    assert rc == _abi.IAT_EINVAL and "hmax" in msg

@@ -1,0 +1,159 @@
+"""GPU parity of iat_integrate (plain and persistent kernels) against the CPU oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests import _parity as PT
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2509_15117_amd as iat  # noqa: E402
+from paper_2509_15117_amd import api  # noqa: E402
+
+KERNELS = ["plain", "persistent"]
+
+
+def run(w, n=None, id0=0, **kw):
+    out = api.integrate_workload(w, n=n, id0=id0, y_final=True, **kw)
+    torch.cuda.synchronize()
+    return PT.to_numpy(out)
+
+
+def oracle_run(w, ids):
+    P = oracle.problems_for(w, ids)
+    return P, oracle.integrate(P)
+
+
+def assert_parity(P, ref, got, name, min_direct=1):
+    direct, spread, rest = PT.classify(P, ref, got)
+    n_strict = int(np.sum(spread <= 0.1 * PT.REL))
+    print(f"{name}: {len(direct)} direct ({n_strict} with round-off spread <= 1e-9, bar 1e-8), "
+          f"{len(rest)} in ensemble", flush=True)
+    assert len(direct) >= min_direct, f"{name}: only {len(direct)} direct trajectories"
+    bad = PT.per_trajectory_mismatches(P, ref, got, direct, check_counts=False, spread=spread)
+    assert not bad, f"{name}: per-trajectory mismatches {bad[:10]} (of {len(direct)})"
+    same = np.mean([got["n_accept"][i] == ref["n_accept"][i] and got["n_reject"][i] == ref["n_reject"][i]
+                    for i in direct]) if len(direct) else 1.0
+    assert same >= 0.99, f"{name}: step counts differ on {1 - same:.1%} of direct trajectories"
+    badE = PT.ensemble_mismatches(ref, got, rest)
+    assert not badE, f"{name}: ensemble mismatches {badE}"
+    return direct, rest
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_config1_grid_parity(kernel):
+    w = W.config1()
+    got = run(w, kernel=kernel)
+    P, ref = oracle_run(w, range(64))
+    print(f"config1 {kernel}: n_bounce {got['n_bounce'].tolist()}", flush=True)
+    direct, rest = assert_parity(P, ref, got, f"config1/{kernel}", min_direct=16)
+    assert len(direct) + len(rest) == 64
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_sweep_parity_ragged(kernel):
+    """1000 sweep ids of the 5-species workload (ragged: not a multiple of 64), id0 offset."""
+    w = W.config3()
+    id0 = 1_234_567
+    got = run(w, n=1000, id0=id0, kernel=kernel)
+    P, ref = oracle_run(w, np.arange(id0, id0 + 1000))
+    assert_parity(P, ref, got, f"sweep/{kernel}", min_direct=400)
+
+
+def test_plain_and_persistent_are_bitwise_identical():
+    for w, n in ((W.config1(), 64), (W.config3(), 3000)):
+        a = run(w, n=n, kernel="plain")
+        for kw in (dict(block=256), dict(block=64, refill_every=4), dict(block=128, blocks_per_cu=1)):
+            b = run(w, n=n, kernel="persistent", **kw)
+            for k in a:
+                assert np.array_equal(a[k], b[k], equal_nan=True), (w.name, kw, k)
+
+
+def test_full_size_grid_sampled_against_oracle():
+    """1024x1024 grid in the benchmark's launch configuration; sampled ids checked one by one."""
+    w = W.config2()
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    out = api.integrate_workload(w, y_final=True, stats=stats)
+    torch.cuda.synchronize()
+    got = PT.to_numpy(out)
+    st = got["status"].astype(np.int64)
+    ends = st & (oracle.EXITED | oracle.TMAX | oracle.H_UNDERFLOW | oracle.NONFINITE | oracle.MAX_STEPS)
+    assert np.all(ends != 0), "every trajectory must end with a stop reason"
+    assert np.all((got["angle"] >= 0) & (got["angle"] <= math.pi))
+    # RHS evaluations: the first stage, 6 per attempted step, 4 x 5 for the exit re-steps
+    ran = (st & (oracle.EXITED | oracle.TMAX)) != 0
+    expect = 1 + 6 * (got["n_accept"] + got["n_reject"]) + np.where(st & oracle.EXITED, 20, 0)
+    assert np.array_equal(got["n_rhs"][ran], expect[ran])
+    s = stats.cpu().numpy()
+    assert s[3] == w.n and s[0] == got["n_rhs"].sum() and s[1] == got["n_accept"].sum()
+    rng = np.random.default_rng(11)
+    ids = np.sort(rng.choice(w.n, size=96, replace=False))
+    P, ref = oracle_run(w, ids)
+    sub = {k: (v[:, ids] if k == "y_final" else v[ids]) for k, v in got.items()}
+    assert_parity(P, ref, sub, "config2-sampled", min_direct=10)
+
+
+def _edge_system(**over):
+    w = W.config1()
+    for k, v in over.items():
+        setattr(w.system, k, v)
+    return w
+
+
+def test_edge_cases_status_flags():
+    w = W.config1()
+    # empty batch: nothing launched, nothing written
+    out = api.integrate_workload(w, n=0)
+    assert all(v.numel() == 0 for v in out.values())
+    # a single trajectory, and a ragged batch
+    for n in (1, 65 - 1):
+        got = run(w, n=n)
+        P, ref = oracle_run(w, range(n))
+        assert np.array_equal(got["n_bounce"], ref["n_bounce"])
+    # tiny t_max -> TMAX + COMPLEX at exactly tau_max
+    wt = _edge_system(t_max=w.system.t_max * 1e-3)
+    got = run(wt, n=8)
+    assert np.all(got["status"] & oracle.TMAX) and np.all(got["status"] & oracle.COMPLEX)
+    P, ref = oracle_run(wt, range(8))
+    assert np.allclose(got["t_dwell"], ref["t_dwell"], rtol=1e-15, atol=0)
+    assert np.array_equal(got["n_accept"], ref["n_accept"])
+    # hmin above h0 -> H_UNDERFLOW before any step
+    got = run(_edge_system(hmin=1.0), n=4)
+    assert np.all(got["status"] & oracle.H_UNDERFLOW) and np.all(got["n_accept"] == 0)
+    # accepted-step cap
+    got = run(_edge_system(max_steps=10), n=4)
+    assert np.all(got["status"] & oracle.MAX_STEPS) and np.all(got["n_accept"] == 10)
+    # Cs at 1 uK violates 10|V(r0)| < E: warning bit, run proceeds
+    cs = W.Workload("cs", 2, W.System(E=W.kelvin(1e-6), max_steps=50), ["Cs133"],
+                    W.Generator(kind="grid", n_theta=1, n_phi=2))
+    got = run(cs)
+    assert np.all(got["status"] & oracle.WARN_R0)
+    # non-finite start state through y0: flagged, no step taken
+    y0 = torch.zeros(12, 3, dtype=torch.float64, device="cuda")
+    y0[:, 0] = float("nan")
+    y0[0, 1:] = 5000.0
+    y0[6, 1:] = -7.7e-9
+    g = W.Generator(kind="arrays")
+    out = api.integrate(w.system, w.species(), g, 3, y0=y0, counters=True)
+    torch.cuda.synchronize()
+    st = out["status"].cpu().numpy()
+    assert st[0] & oracle.NONFINITE and out["n_rhs"][0].item() == 0
+    assert st[1] & oracle.EXITED and st[2] & oracle.EXITED
+
+
+def test_arrays_mode_matches_grid_mode():
+    w = W.config1()
+    th_ph = oracle.grid_angles(range(64), 8, 8)
+    arrays = {"theta": torch.tensor(th_ph[:, 0], device="cuda"), "phi": torch.tensor(th_ph[:, 1], device="cuda")}
+    g = W.Generator(kind="arrays")
+    a = PT.to_numpy(api.integrate(w.system, w.species(), g, 64, arrays=arrays, y_final=True))
+    b = run(w)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
