@@ -140,17 +140,23 @@ typedef struct {
 enum { IAT_KERNEL_PLAIN = 1, IAT_KERNEL_PERSISTENT = 2 };
 
 /* Launch shape.  kernel: PLAIN = one lane per trajectory, one launch per batch;
- * PERSISTENT = resident grid whose lanes refill from a device work queue.
+ * PERSISTENT = resident grid whose lanes refill from a device work queue; trajectories that
+ * outlive step_budget continue four lanes per trajectory in a second kernel.  Both kernels
+ * give the same bits for the same trajectory.
  * Zero fields take defaults.  stats, if not NULL, is a device uint64[8] to which the
  * call ADDS: [0] RHS evaluations, [1] accepted steps, [2] rejected steps,
  * [3] trajectories finished, [4] issued lane-steps (wave iterations x 64),
  * [5] useful lane-steps (attempted steps). */
 typedef struct {
     int32_t kernel;
-    int32_t block;            /* threads per block (multiple of 64, <= 1024)           */
+    int32_t block;            /* threads per block: 64, 128, 192 or 256                */
     int32_t blocks_per_cu;    /* PERSISTENT: resident blocks per CU (0 = occupancy max) */
     int32_t refill_every;     /* PERSISTENT: attempted steps between refills (>= 1)    */
-    int32_t reserved[4];
+    int32_t step_budget;      /* PERSISTENT: attempted steps after which an unfinished
+                                 trajectory is suspended and finished by four lanes (one
+                                 per axis) to cut the latency of long-lived complexes;
+                                 0 = default (20000), -1 = never                         */
+    int32_t reserved[3];
     uint64_t* stats;
 } iat_launch;
 

@@ -330,7 +330,8 @@ static int integrate_impl(const orc_problem* p, orc_result* R, double* hrec, int
             }
             if (r_prev <= r0 && r_new > r0 && s_new > 0.0) {
                 double hs = exit_locate(&S, tau, y, k, h, r_prev, r_new, r0, yend, &nrhs);
-                if (hrec) { if (n_acc <= cap) hrec[n_acc - 1] = hs; else rec_overflow = 1; }
+                /* the located exit step, followed by the full size of that step */
+                if (hrec) { if (n_acc < cap) { hrec[n_acc - 1] = hs; hrec[n_acc] = h; } else rec_overflow = 1; }
                 tau = tau + hs;
                 status |= ORC_EXITED;
                 memcpy(y, yend, sizeof(y));

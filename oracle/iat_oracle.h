@@ -68,7 +68,8 @@ int  orc_integrate(const orc_problem* p, orc_result* r);
 void orc_integrate_batch(int64_t n, const orc_problem* p, orc_result* r, int nthreads);
 /* Same as orc_integrate, also recording the accepted step sizes (internal time):
    h[0 .. n_accept-2] are the whole accepted steps, h[n_accept-1] the last one (the
-   located exit step when the run exited).  Returns -1 if cap is too small. */
+   located exit step when the run exited, and then h[n_accept] is the full size of the step
+   that crossed r0).  Returns -1 if cap is too small. */
 int  orc_integrate_record(const orc_problem* p, orc_result* r, double* h, int64_t cap);
 
 /* initial conditions */

@@ -108,17 +108,18 @@ def batch_struct(n: int, gen, arrays: Optional[Dict[str, torch.Tensor]] = None,
     return b
 
 
-def launch_struct(kernel="persistent", block=0, blocks_per_cu=0, refill_every=0,
+def launch_struct(kernel="persistent", block=0, blocks_per_cu=0, refill_every=0, step_budget=0,
                   stats: Optional[torch.Tensor] = None) -> _abi.Launch:
     L = _abi.Launch()
     L.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     L.block, L.blocks_per_cu, L.refill_every = block, blocks_per_cu, refill_every
+    L.step_budget = step_budget
     L.stats = _ptr(stats)
     return L
 
 
 def integrate(system, species, gen, n: int, *, arrays=None, y0=None, id0=None, kernel="persistent", block=0,
-              blocks_per_cu=0, refill_every=0, y_final=False, counters=True, stats=None, out=None,
+              blocks_per_cu=0, refill_every=0, step_budget=0, y_final=False, counters=True, stats=None, out=None,
               stream=None, device=None) -> Dict[str, torch.Tensor]:
     """Integrate n trajectories on the current GPU; returns device tensors of the observables.
 
@@ -132,7 +133,7 @@ def integrate(system, species, gen, n: int, *, arrays=None, y0=None, id0=None, k
     sp = species_array(species)
     b = batch_struct(n, gen, arrays, y0, id0)
     o = obs_struct(out)
-    la = launch_struct(kernel, block, blocks_per_cu, refill_every, stats)
+    la = launch_struct(kernel, block, blocks_per_cu, refill_every, step_budget, stats)
     rc = L.iat_integrate(ctypes.byref(sysv), sp, len(species), ctypes.byref(b), ctypes.byref(o), ctypes.byref(la),
                          None, 0, _stream_handle(stream))
     _abi.check(rc)

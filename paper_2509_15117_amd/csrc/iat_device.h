@@ -78,6 +78,7 @@ struct KParams {
     double* y_final;
     uint64_t* stats;
     int32_t refill_every;
+    int64_t budget;              // attempted steps before suspension (0: never)
 };
 
 // Species table lookup by select (no dynamic indexing into the kernel-argument block).
@@ -234,26 +235,91 @@ __device__ inline void lane_consts(const KParams& P, const TrajParams& t, Lane& 
 }
 
 // ---------------------------------------------------------------------------------------
-// Equations of motion (Eq. (1)) in internal units.  d = r_a - r_i, u = 1/|d|^2;
-// force on the atom F = (8 C8' u^5 - 4 C4' u^3) d; atom a = F/m_a; ion a = -F/m_i - kappa o r_i
-// with kappa_k = (a_k + 2 q_k cos(tau + phase0))/4.  `cs` is cos(tau + phase0).
+// Per-component expressions.  Every arithmetic expression of a step is written once here and
+// used by both forms of the step: one lane per trajectory (all 12 components in one lane) and
+// four lanes per trajectory (lane k of a quad holds the atom and ion components of axis k).
+// With contraction decided per source expression, both forms produce the same bits.
 // ---------------------------------------------------------------------------------------
-__device__ __forceinline__ void accel(const KParams& P, const Lane& L, double cs, const double X[6], double A[6])
+
+// 1/x by the hardware reciprocal refined with two Newton steps (x > 0, normal).
+__device__ __forceinline__ double recip(double x)
 {
-    const double d0 = X[0] - X[3], d1 = X[1] - X[4], d2 = X[2] - X[5];
-    const double rho = d0 * d0 + d1 * d1 + d2 * d2;
-    const double u = 1.0 / rho;
-    const double u2 = u * u;
-    const double s = u2 * u * (L.c8x8 * u2 - L.c4x4);
-    const double qc = L.qx_half * cs;
-    const double F0 = s * d0, F1 = s * d1, F2 = s * d2;
-    A[0] = F0 * L.inv_ma;
-    A[1] = F1 * L.inv_ma;
-    A[2] = F2 * L.inv_ma;
-    A[3] = -F0 * P.inv_mi - (P.kA[0] + qc * P.q_ratio[0]) * X[3];
-    A[4] = -F1 * P.inv_mi - (P.kA[1] + qc * P.q_ratio[1]) * X[4];
-    A[5] = -F2 * P.inv_mi - (P.kA[2] + qc * P.q_ratio[2]) * X[5];
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
 }
+
+__device__ __forceinline__ double dot3(double a0, double a1, double a2, double b0, double b1, double b2)
+{
+    return a0 * b0 + a1 * b1 + a2 * b2;
+}
+
+// Equations of motion (Eq. (1)) in internal units.  d = r_a - r_i, u = 1/|d|^2; the force on
+// the atom is F = s d with s = 8 C8' u^5 - 4 C4' u^3; atom acceleration F/m_a; ion acceleration
+// -F/m_i - kappa_k r_i,k with kappa_k = (a_k + 2 q_k cos(tau + phase0))/4 = kA_k + qc qr_k,
+// qc = (q_x/2) cos(tau + phase0).
+__device__ __forceinline__ double force_scale(const Lane& L, double d0, double d1, double d2)
+{
+    const double u = recip(dot3(d0, d1, d2, d0, d1, d2));
+    const double u2 = u * u;
+    return u2 * u * (L.c8x8 * u2 - L.c4x4);
+}
+__device__ __forceinline__ double acc_atom(const Lane& L, double s, double dk) { return (s * dk) * L.inv_ma; }
+__device__ __forceinline__ double acc_ion(double inv_mi, double s, double dk, double kA, double qc, double qr,
+                                          double xi)
+{
+    return -(s * dk) * inv_mi - (kA + qc * qr) * xi;
+}
+
+// Stage positions X_s = x + c_s h v + h^2 sum_j (A^2)_sj F_j, fifth-order solution and error.
+__device__ __forceinline__ double stage2(double x, double v, double h) { return x + (c2 * h) * v; }
+__device__ __forceinline__ double stage3(double x, double v, double h, double hh, double f1)
+{
+    return x + (c3 * h) * v + hh * (p31 * f1);
+}
+__device__ __forceinline__ double stage4(double x, double v, double h, double hh, double f1, double f2)
+{
+    return x + (c4 * h) * v + hh * (p41 * f1 + p42 * f2);
+}
+__device__ __forceinline__ double stage5(double x, double v, double h, double hh, double f1, double f2, double f3)
+{
+    return x + (c5 * h) * v + hh * (p51 * f1 + p52 * f2 + p53 * f3);
+}
+__device__ __forceinline__ double stage6(double x, double v, double h, double hh, double f1, double f2, double f3,
+                                         double f4)
+{
+    return x + h * v + hh * (p61 * f1 + p62 * f2 + p63 * f3 + p64 * f4);
+}
+__device__ __forceinline__ double sol_x(double x, double v, double h, double hh, double f1, double f2, double f3,
+                                        double f4, double f5)
+{
+    return x + h * v + hh * (q1 * f1 + q2 * f2 + q3 * f3 + q4 * f4 + q5 * f5);
+}
+__device__ __forceinline__ double sol_v(double v, double h, double f1, double f3, double f4, double f5, double f6)
+{
+    return v + h * (b1 * f1 + b3 * f3 + b4 * f4 + b5 * f5 + b6 * f6);
+}
+__device__ __forceinline__ double err_x(double hh, double f1, double f2, double f3, double f4, double f5, double f6)
+{
+    return hh * (r1 * f1 + r2 * f2 + r3 * f3 + r4 * f4 + r5 * f5 + r6 * f6);
+}
+__device__ __forceinline__ double err_v(double h, double f1, double f3, double f4, double f5, double f6, double f7)
+{
+    const double e = h * (e1 * f1 + e3 * f3 + e4 * f4 + e5 * f5 + e6 * f6);
+    return e + h * (e7 * f7);
+}
+// |err_k| / (atol + rtol max(|y_k|, |y5_k|)) with a refined hardware reciprocal
+__device__ __forceinline__ double err_ratio(double e, double y, double y5, double rtol, double atol)
+{
+    const double sc = atol + rtol * fmax(fabs(y), fabs(y5));
+    double r = __builtin_amdgcn_rcp(sc);
+    r = fma(r, fma(-sc, r, 1.0), r);
+    return fabs(e) * r;
+}
+__device__ __forceinline__ bool ratio_bad(double r) { return !(r <= 1.0e300); }
+__device__ __forceinline__ bool is_finite(double x) { return __builtin_isfinite(x); }
 
 // cos and sin of a stage offset 0 <= d <= pi/4 (steps never exceed an eighth of the RF
 // period): Maclaurin series through d^16 and d^17; the first omitted terms are below 3e-18.
@@ -283,6 +349,40 @@ __device__ __forceinline__ void small_sincos(double d, double& c, double& s)
     s = d + d * (ps * z);
 }
 
+// sin and cos of an RF phase 0 <= x < 1.6e6: Cody-Waite reduction x = k pi/2 + r with pi/2
+// split into P1 + P2 + P3 (33, 33 and 53 significant bits, so k P1 and k P2 are exact for
+// |k| < 2^20), then the Maclaurin polynomials on |r| <= pi/4 and the quadrant k mod 4.
+__device__ __forceinline__ void phase_sincos(double x, double& s, double& c)
+{
+    constexpr double kTwoOverPi = 0.63661977236758134308;
+    constexpr double P1 = 0x1.921fb54400000p+0, P2 = 0x1.0b4611a600000p-34, P3 = 0x1.3198a2e037073p-69;
+    const double k = rint(x * kTwoOverPi);
+    double r = fma(-k, P1, x);
+    r = fma(-k, P2, r);
+    r = fma(-k, P3, r);
+    double cr, sr;
+    small_sincos(r, cr, sr);
+    const int q = ((int)k) & 3;
+    const double a = (q & 1) ? cr : sr, b = (q & 1) ? sr : cr;   // sin, cos up to sign
+    s = (q & 2) ? -a : a;
+    c = ((q + 1) & 2) ? -b : b;
+}
+
+// en^(-1/5) for en >= 1e-4: single-precision estimate from the hardware log2/exp2, refined by
+// two Newton steps on g(y) = en y^5 - 1 (the relative error goes 1e-7 -> 3e-14 -> rounding).
+__device__ __forceinline__ double inv_fifth_root(double en)
+{
+    const float ef = (float)en;
+    double y = (double)__builtin_amdgcn_exp2f(-0.2f * __builtin_amdgcn_logf(ef));
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double y2 = y * y;
+        const double t = fma(-en, y2 * y2 * y, 1.0);
+        y = fma(0.2 * y, t, y);
+    }
+    return y;
+}
+
 // cos(theta + d) from cos/sin(theta) and the stage offset d
 __device__ __forceinline__ double cos_shift(double cb, double sb, double d)
 {
@@ -291,267 +391,501 @@ __device__ __forceinline__ double cos_shift(double cb, double sb, double d)
     return cb * c - sb * s;
 }
 
-// One Dormand-Prince step of size h from (tau, x, v) with F1 = accel(tau, x).
-// Always produces the fifth-order (x5, v5).  With fsal it also evaluates the last stage
-// F7 = accel(tau + h, x5) and returns the max-norm error ratio
-//   en = max_k |err_k| / (atol + rtol max(|y_k|, |y5_k|))   (NaN if anything is non-finite);
-// without it (exit re-steps) it returns 0 after five new evaluations.
-__device__ __forceinline__ double dp5_step(const KParams& P, const Lane& L, bool fsal, double tau, double h,
-                                           const double x[6], const double v[6], const double F1[6],
-                                           double x5[6], double v5[6], double F7[6])
+// Cosines of the RF phase at the stage times tau + c_s h (s = 2..6; stage 7 shares c = 1).
+struct StageCos {
+    double c2, c3, c4, c5, c6;
+};
+__device__ __forceinline__ StageCos stage_cos(double tau, double phase0, double h)
 {
-    const double hh = h * h;
     double sb, cb;
-    sincos(tau + L.phase0, &sb, &cb);
-    double F2[6], F3[6], F4[6], F5[6], F6[6], X[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) X[k] = x[k] + (c2 * h) * v[k];
-    accel(P, L, cos_shift(cb, sb, c2 * h), X, F2);
-    // stage velocities are not needed: only positions enter the accelerations
-#pragma unroll
-    for (int k = 0; k < 6; ++k) X[k] = x[k] + (c3 * h) * v[k] + hh * (p31 * F1[k]);
-    accel(P, L, cos_shift(cb, sb, c3 * h), X, F3);
-#pragma unroll
-    for (int k = 0; k < 6; ++k) X[k] = x[k] + (c4 * h) * v[k] + hh * (p41 * F1[k] + p42 * F2[k]);
-    accel(P, L, cos_shift(cb, sb, c4 * h), X, F4);
-#pragma unroll
-    for (int k = 0; k < 6; ++k)
-        X[k] = x[k] + (c5 * h) * v[k] + hh * (p51 * F1[k] + p52 * F2[k] + p53 * F3[k]);
-    accel(P, L, cos_shift(cb, sb, c5 * h), X, F5);
-#pragma unroll
-    for (int k = 0; k < 6; ++k)
-        X[k] = x[k] + h * v[k] + hh * (p61 * F1[k] + p62 * F2[k] + p63 * F3[k] + p64 * F4[k]);
-    const double cs_end = cos_shift(cb, sb, h);
-    accel(P, L, cs_end, X, F6);
-    double ex[6], ev[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        x5[k] = x[k] + h * v[k] + hh * (q1 * F1[k] + q2 * F2[k] + q3 * F3[k] + q4 * F4[k] + q5 * F5[k]);
-        v5[k] = v[k] + h * (b1 * F1[k] + b3 * F3[k] + b4 * F4[k] + b5 * F5[k] + b6 * F6[k]);
-        ex[k] = hh * (r1 * F1[k] + r2 * F2[k] + r3 * F3[k] + r4 * F4[k] + r5 * F5[k] + r6 * F6[k]);
-        ev[k] = h * (e1 * F1[k] + e3 * F3[k] + e4 * F4[k] + e5 * F5[k] + e6 * F6[k]);
-    }
-    if (!fsal) return 0.0;
-    accel(P, L, cs_end, x5, F7);
-#pragma unroll
-    for (int k = 0; k < 6; ++k) ev[k] += h * (e7 * F7[k]);
-    // max_k |err_k| / sc_k located by cross-multiplication (sc_k > 0), then one division
-    double num = 0.0, den = 1.0;
-    bool bad = false;
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-        const double yk = k < 6 ? x[k] : v[k - 6];
-        const double y5k = k < 6 ? x5[k] : v5[k - 6];
-        const double ek = fabs(k < 6 ? ex[k] : ev[k - 6]);
-        const double sc = P.atol + P.rtol * fmax(fabs(yk), fabs(y5k));
-        bad |= !(ek <= 1.0e300) || !(sc <= 1.0e300);
-        const bool gt = ek * den > num * sc;
-        num = gt ? ek : num;
-        den = gt ? sc : den;
-    }
-    return bad ? __builtin_nan("") : num / den;
+    phase_sincos(tau + phase0, sb, cb);
+    StageCos C;
+    C.c2 = cos_shift(cb, sb, c2 * h);
+    C.c3 = cos_shift(cb, sb, c3 * h);
+    C.c4 = cos_shift(cb, sb, c4 * h);
+    C.c5 = cos_shift(cb, sb, c5 * h);
+    C.c6 = cos_shift(cb, sb, h);
+    return C;
 }
 
-// Trajectory state carried across steps.  mode 0: stepping; mode 1..4: the lane is locating
-// the exit crossing (secant iterate mode), holding the step start y_n in x, v, F1.
-struct Traj {
-    double x[6], v[6], F1[6];
+// bound-state test 1/2 mu v_rel^2 + C8'/rho^4 - C4'/rho^2 < 0 (rho = r^2), multiplied through
+// by rho^4 > 0 so that no division is needed
+__device__ __forceinline__ bool bound_state(const Lane& L, double rho, double w2)
+{
+    const double rho2 = rho * rho;
+    return L.half_mu * w2 * (rho2 * rho2) + 0.125 * L.c8x8 - 0.25 * L.c4x4 * rho2 < 0.0;
+}
+
+// Step factors min(5, max(0.2, 0.9 en^(-1/5))), capped at 1 right after a rejection; below
+// en = 1.8e-4 the factor is 5 whatever en is ((0.9/5)^5 = 1.89e-4).
+__device__ __forceinline__ double step_factor(double en, bool last_rej)
+{
+    const double fac = en < 1.8e-4 ? 5.0 : fmin(5.0, fmax(0.2, 0.9 * inv_fifth_root(en)));
+    return last_rej ? fmin(1.0, fac) : fac;
+}
+__device__ __forceinline__ double reject_factor(double en)
+{
+    return (en != en) ? 0.2 : fmax(0.2, 0.9 * inv_fifth_root(en));
+}
+
+// ---------------------------------------------------------------------------------------
+// Trajectory state carried across steps.  mode 0: stepping; mode 1..4: the trajectory is
+// locating its exit crossing (secant iterate mode), holding the step start y_n.
+// The scalar part is the same for both forms; the vector part is 12 components (one lane)
+// or the 4 components of one axis (four lanes).
+// ---------------------------------------------------------------------------------------
+struct Scal {
     double tau, h;
-    double rho_prev, s_prev;     // separation^2 and sign carrier of d(separation)/dt at y_n
-    double sx1, sg1;             // secant: latest iterate (the previous one is in rho_prev/s_prev)
+    double rho_prev, s_prev;     // separation^2 and the sign carrier of its rate at y_n
+    double sx1, sg1;             // secant: latest iterate (the previous one sits in rho_prev/s_prev)
     double tau_first, tau_last;
     int32_t nacc, nrej, nrhs, nb;
     uint32_t status, mode;
-    bool last_rej, done;
+    int32_t last_rej, done;
+};
+
+__device__ inline void scal_init(const KParams& P, Scal& S)
+{
+    S.tau = 0.0;
+    S.tau_first = S.tau_last = 0.0;
+    S.sx1 = S.sg1 = 0.0;
+    S.nacc = S.nrej = 0;
+    S.nrhs = 0;
+    S.nb = 0;
+    S.mode = 0;
+    S.last_rej = 0;
+    S.done = 0;
+    S.h = P.h0 < P.hmax ? P.h0 : P.hmax;
+    S.rho_prev = S.s_prev = 0.0;
+}
+
+// asymptotic-start condition 10 |V(r0)| < E (head-on-run paragraph), on the a.u. start state
+__device__ inline bool warn_r0(const KParams& P, const TrajParams& tp, const double y[12])
+{
+    const double ma = species_mass(P, tp.sp);
+    const double ek = 0.5 * ma * (y[6] * y[6] + y[7] * y[7] + y[8] * y[8]);
+    const double C4 = species_C4(P, tp.sp), C8 = C4 * C4 / (4.0 * tp.De);
+    const double d0 = y[0] - y[3], d1 = y[1] - y[4], d2 = y[2] - y[5];
+    const double r2 = d0 * d0 + d1 * d1 + d2 * d2, r4 = r2 * r2;
+    const double V = C8 / (r4 * r4) - C4 / r4;
+    return !(10.0 * fabs(V) < ek);
+}
+
+// Step prologue shared by both forms: picks h and handles the stops that precede a step.
+// Returns false when the trajectory stopped.
+__device__ __forceinline__ bool step_prologue(const KParams& P, Scal& S, double& h, bool& fin)
+{
+    fin = false;
+    if (S.mode != 0) {
+        const double x0 = S.rho_prev, g0 = S.s_prev, x1 = S.sx1, g1 = S.sg1;
+        h = (g1 != g0) ? x1 - g1 * (x1 - x0) / (g1 - g0) : x1;
+        h = h < 0.0 ? 0.0 : (h > S.h ? S.h : h);
+        return true;
+    }
+    if (S.nacc >= P.max_steps) {
+        S.status |= IAT_ST_MAX_STEPS;
+        S.done = 1;
+        return false;
+    }
+    h = S.h;
+    if (h >= P.tau_max - S.tau) {
+        h = P.tau_max - S.tau;
+        fin = true;
+    }
+    if (!fin && h < P.hmin) {
+        S.status |= IAT_ST_H_UNDERFLOW;
+        S.done = 1;
+        return false;
+    }
+    return true;
+}
+
+// What an attempted (or secant) step decided.
+enum StepOutcome { OUT_SECANT_CONT = 0, OUT_SECANT_DONE, OUT_REJECT, OUT_NONFINITE, OUT_ACCEPT, OUT_STOP_RFLOOR,
+                   OUT_ENTER_EXIT, OUT_TMAX };
+
+// Bookkeeping after a step, shared by both forms.  g: separation minus r0 of the new state
+// (secant mode) ; rho_new, s_new, w2: geometry of the new state (normal mode); fin: final step.
+__device__ __forceinline__ StepOutcome step_epilogue(const KParams& P, Scal& S, const Lane& L, double h, bool fin,
+                                                     double en, bool finite, double rho_new, double s_new,
+                                                     double w2)
+{
+    if (S.mode != 0) {
+        S.nrhs += 5;
+        const double g2 = sqrt(rho_new) - P.r0;
+        S.rho_prev = S.sx1;
+        S.s_prev = S.sg1;
+        S.sx1 = h;
+        S.sg1 = g2;
+        if (++S.mode > 4) {
+            S.tau = S.tau + h;
+            S.status |= IAT_ST_EXITED;
+            S.done = 1;
+            return OUT_SECANT_DONE;
+        }
+        return OUT_SECANT_CONT;
+    }
+    S.nrhs += 6;
+    if (!(en <= 1.0)) {
+        S.nrej++;
+        S.h = h * reject_factor(en);
+        S.last_rej = 1;
+        return OUT_REJECT;
+    }
+    S.nacc++;
+    if (!finite) {
+        S.status |= IAT_ST_NONFINITE;
+        S.done = 1;
+        return OUT_NONFINITE;
+    }
+    const double tau_new = fin ? P.tau_max : S.tau + h;
+    // bounce: periapsis of the relative motion inside r_b
+    if (S.s_prev < 0.0 && s_new >= 0.0 && fmin(S.rho_prev, rho_new) < L.rm2 * P.rb_ratio2) {
+        if (S.nb == 0) S.tau_first = tau_new;
+        S.tau_last = tau_new;
+        S.nb++;
+    }
+    if (bound_state(L, rho_new, w2)) S.status |= IAT_ST_BOUND_SEEN;
+    if (rho_new < 0.01 * L.rm2) {   // separation below 0.1 r_m: integration broken
+        S.tau = tau_new;
+        S.status |= IAT_ST_R_UNDERFLOW;
+        S.done = 1;
+        return OUT_STOP_RFLOOR;
+    }
+    if (S.rho_prev <= P.r0sq && rho_new > P.r0sq && s_new > 0.0) {
+        // keep y_n; the next four steps are secant iterates, (x0, g0) kept in (rho_prev, s_prev)
+        S.mode = 1;
+        S.s_prev = sqrt(S.rho_prev) - P.r0;
+        S.rho_prev = 0.0;
+        S.sx1 = h;
+        S.sg1 = sqrt(rho_new) - P.r0;
+        S.h = h;
+        return OUT_ENTER_EXIT;
+    }
+    S.tau = tau_new;
+    S.rho_prev = rho_new;
+    S.s_prev = s_new;
+    if (fin) {
+        S.status |= IAT_ST_TMAX;
+        S.done = 1;
+        S.h = h;
+        return OUT_TMAX;
+    }
+    S.h = fmin(P.hmax, h * step_factor(en, S.last_rej != 0));
+    S.last_rej = 0;
+    return OUT_ACCEPT;
+}
+
+// ---------------------------------------------------------------------------------------
+// One lane per trajectory.
+// ---------------------------------------------------------------------------------------
+struct Traj1 {
+    double x[6], v[6], F1[6];   // r_atom, r_ion ; v_atom, v_ion ; accelerations at y_n
+    Scal S;
     Lane L;
 };
 
-__device__ __forceinline__ double sep2(const double x[6])
+__device__ __forceinline__ void accel1(const KParams& P, const Lane& L, double cs, const double X[6], double A[6])
 {
-    const double d0 = x[0] - x[3], d1 = x[1] - x[4], d2 = x[2] - x[5];
-    return d0 * d0 + d1 * d1 + d2 * d2;
-}
-__device__ __forceinline__ double radial_sign(const double x[6], const double v[6])
-{
-    return (x[0] - x[3]) * (v[0] - v[3]) + (x[1] - x[4]) * (v[1] - v[4]) + (x[2] - x[5]) * (v[2] - v[5]);
+    const double d0 = X[0] - X[3], d1 = X[1] - X[4], d2 = X[2] - X[5];
+    const double s = force_scale(L, d0, d1, d2);
+    const double qc = L.qx_half * cs;
+    A[0] = acc_atom(L, s, d0);
+    A[1] = acc_atom(L, s, d1);
+    A[2] = acc_atom(L, s, d2);
+    A[3] = acc_ion(P.inv_mi, s, d0, P.kA[0], qc, P.q_ratio[0], X[3]);
+    A[4] = acc_ion(P.inv_mi, s, d1, P.kA[1], qc, P.q_ratio[1], X[4]);
+    A[5] = acc_ion(P.inv_mi, s, d2, P.kA[2], qc, P.q_ratio[2], X[5]);
 }
 
-__device__ inline void traj_start(const KParams& P, int64_t i, Traj& T)
+// Runs once per trajectory.
+// ---------------------------------------------------------------------------------------
+// Per-call work buffer, structure of arrays over the n trajectories of a call:
+//   D[0..11]  internal state x[6] (r_atom, r_ion), v[6] (v_atom, v_ion): the start state on
+//             entry to the integration kernels, the final state on exit
+//   D[12..18] lane constants (inv_ma, c8x8, c4x4, qx_half, phase0, rm2, half_mu)
+//   D[19..21] tau, tau_first, tau_last (final)
+//   I[0..4]   nacc, nrej, nrhs, n_bounce, status
+// A setup kernel fills the start, the integration kernels only load, step and store, and an
+// observables kernel turns the final state into the outputs, so the step loops carry nothing
+// but the step.
+// ---------------------------------------------------------------------------------------
+struct Work {
+    double* D;
+    int32_t* I;
+    int64_t n;
+    __device__ __forceinline__ double& d(int f, int64_t i) const { return D[(int64_t)f * n + i]; }
+    __device__ __forceinline__ int32_t& k(int f, int64_t i) const { return I[(int64_t)f * n + i]; }
+};
+constexpr int kWorkDoubles = 22, kWorkInts = 5;
+
+__device__ inline void work_setup(const KParams& P, const Work& W, int64_t i)
 {
     TrajParams tp;
     traj_params(P, i, tp);
-    lane_consts(P, tp, T.L);
+    Lane L;
+    lane_consts(P, tp, L);
     double y[12];
     start_state_au(P, i, tp, y);
-    T.status = 0;
-    {   // asymptotic-start condition 10 |V(r0)| < E (head-on-run paragraph)
-        const double ma = species_mass(P, tp.sp);
-        const double ek = 0.5 * ma * (y[6] * y[6] + y[7] * y[7] + y[8] * y[8]);
-        const double C4 = species_C4(P, tp.sp), C8 = C4 * C4 / (4.0 * tp.De);
-        const double d0 = y[0] - y[3], d1 = y[1] - y[4], d2 = y[2] - y[5];
-        const double r2 = d0 * d0 + d1 * d1 + d2 * d2, r4 = r2 * r2;
-        const double V = C8 / (r4 * r4) - C4 / r4;
-        if (!(10.0 * fabs(V) < ek)) T.status |= IAT_ST_WARN_R0;
-    }
-#pragma unroll
     for (int k = 0; k < 6; ++k) {
-        T.x[k] = y[k];
-        T.v[k] = y[6 + k] / P.omega;
+        W.d(k, i) = y[k];
+        W.d(6 + k, i) = y[6 + k] / P.omega;
     }
-    T.tau = 0.0;
-    T.tau_first = T.tau_last = 0.0;
-    T.sx1 = T.sg1 = 0.0;
-    T.nacc = T.nrej = 0;
-    T.nb = 0;
-    T.mode = 0;
-    T.last_rej = false;
-    T.done = false;
-    double fin = 0.0;
-#pragma unroll
-    for (int k = 0; k < 6; ++k) fin += T.x[k] + T.v[k];
-    if (!__builtin_isfinite(fin)) {
-        T.status |= IAT_ST_NONFINITE;
-        T.done = true;
-        T.nrhs = 0;
-        T.h = 0.0;
-        T.rho_prev = T.s_prev = 0.0;
-        return;
-    }
-    accel(P, T.L, cos(T.L.phase0), T.x, T.F1);
-    T.nrhs = 1;
-    T.h = P.h0 < P.hmax ? P.h0 : P.hmax;
-    T.rho_prev = sep2(T.x);
-    T.s_prev = radial_sign(T.x, T.v);
+    W.d(12, i) = L.inv_ma;
+    W.d(13, i) = L.c8x8;
+    W.d(14, i) = L.c4x4;
+    W.d(15, i) = L.qx_half;
+    W.d(16, i) = L.phase0;
+    W.d(17, i) = L.rm2;
+    W.d(18, i) = L.half_mu;
+    W.k(4, i) = (int32_t)(warn_r0(P, tp, y) ? IAT_ST_WARN_R0 : 0u);
 }
 
-// One attempted step plus the events of an accepted step, or one secant iterate of the exit
-// location.  Exit location: once an accepted step y_n -> y_{n+1} carries the separation across
-// r0 outward, four secant iterations on g(h*) = |r(RK5(y_n, h*))| - r0 follow, each a fresh
-// step from y_n, starting from the linear interpolation between the step ends; the last
-// iterate is the final state.
-__device__ __forceinline__ void traj_advance(const KParams& P, Traj& T)
+__device__ __forceinline__ void work_lane(const Work& W, int64_t i, Lane& L)
 {
-    double h;
-    bool fin = false;
-    const bool exiting = T.mode != 0;
-    if (exiting) {
-        const double x0 = T.rho_prev, g0 = T.s_prev, x1 = T.sx1, g1 = T.sg1;
-        h = (g1 != g0) ? x1 - g1 * (x1 - x0) / (g1 - g0) : x1;
-        h = h < 0.0 ? 0.0 : (h > T.h ? T.h : h);
-    } else {
-        if (T.nacc >= P.max_steps) {
-            T.status |= IAT_ST_MAX_STEPS;
-            T.done = true;
-            return;
-        }
-        h = T.h;
-        if (h >= P.tau_max - T.tau) {
-            h = P.tau_max - T.tau;
-            fin = true;
-        }
-        if (!fin && h < P.hmin) {
-            T.status |= IAT_ST_H_UNDERFLOW;
-            T.done = true;
-            return;
-        }
-    }
-    double x5[6], v5[6], F7[6];
-    const double en = dp5_step(P, T.L, !exiting, T.tau, h, T.x, T.v, T.F1, x5, v5, F7);
-    if (exiting) {
-        T.nrhs += 5;
-        const double g2 = sqrt(sep2(x5)) - P.r0;
-        T.rho_prev = T.sx1;
-        T.s_prev = T.sg1;
-        T.sx1 = h;
-        T.sg1 = g2;
-        if (++T.mode > 4) {
+    L.inv_ma = W.d(12, i);
+    L.c8x8 = W.d(13, i);
+    L.c4x4 = W.d(14, i);
+    L.qx_half = W.d(15, i);
+    L.phase0 = W.d(16, i);
+    L.rm2 = W.d(17, i);
+    L.half_mu = W.d(18, i);
+}
+
+__device__ __forceinline__ void work_store_scal(const Work& W, int64_t i, const Scal& S)
+{
+    W.d(19, i) = S.tau;
+    W.d(20, i) = S.tau_first;
+    W.d(21, i) = S.tau_last;
+    W.k(0, i) = S.nacc;
+    W.k(1, i) = S.nrej;
+    W.k(2, i) = S.nrhs;
+    W.k(3, i) = S.nb;
+    W.k(4, i) = (int32_t)S.status;
+}
+
+__device__ inline void traj1_start(const KParams& P, const Work& W, int64_t i, Traj1& T)
+{
+    work_lane(W, i, T.L);
+    scal_init(P, T.S);
+    T.S.status = (uint32_t)W.k(4, i);
+    bool fin = true;
 #pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                T.x[k] = x5[k];
-                T.v[k] = v5[k];
-            }
-            T.tau = T.tau + h;
-            T.status |= IAT_ST_EXITED;
-            T.done = true;
-        }
+    for (int k = 0; k < 6; ++k) {
+        T.x[k] = W.d(k, i);
+        T.v[k] = W.d(6 + k, i);
+        fin = fin && is_finite(T.x[k]) && is_finite(T.v[k]);
+    }
+    if (!fin) {
+        T.S.status |= IAT_ST_NONFINITE;
+        T.S.done = 1;
         return;
     }
-    T.nrhs += 6;
-    if (en <= 1.0) {
-        T.nacc++;
-        double fs = 0.0;
+    double s0, c0;
+    phase_sincos(T.L.phase0, s0, c0);
+    accel1(P, T.L, c0, T.x, T.F1);
+    T.S.nrhs = 1;
+    const double d0 = T.x[0] - T.x[3], d1 = T.x[1] - T.x[4], d2 = T.x[2] - T.x[5];
+    T.S.rho_prev = dot3(d0, d1, d2, d0, d1, d2);
+    T.S.s_prev = dot3(d0, d1, d2, T.v[0] - T.v[3], T.v[1] - T.v[4], T.v[2] - T.v[5]);
+}
+
+__device__ __forceinline__ void traj1_store(const Work& W, int64_t i, const Traj1& T)
+{
 #pragma unroll
-        for (int k = 0; k < 6; ++k) fs += x5[k] + v5[k];
-        if (!__builtin_isfinite(fs)) {
-            T.status |= IAT_ST_NONFINITE;
-            T.done = true;
-            return;
-        }
-        const double tau_new = fin ? P.tau_max : T.tau + h;
-        const double rho_new = sep2(x5), s_new = radial_sign(x5, v5);
-        // bounce: periapsis of the relative motion inside r_b
-        if (T.s_prev < 0.0 && s_new >= 0.0 && fmin(T.rho_prev, rho_new) < T.L.rm2 * P.rb_ratio2) {
-            if (T.nb == 0) T.tau_first = tau_new;
-            T.tau_last = tau_new;
-            T.nb++;
-        }
-        // bound-state test: 1/2 mu v_rel^2 + C8'/rho^4 - C4'/rho^2 < 0 (rho = r^2), taken
-        // multiplied through by rho^4 > 0 so that no division is needed
-        {
-            const double w0 = v5[0] - v5[3], w1 = v5[1] - v5[4], w2 = v5[2] - v5[5];
-            const double rho2 = rho_new * rho_new;
-            if (T.L.half_mu * (w0 * w0 + w1 * w1 + w2 * w2) * (rho2 * rho2) + 0.125 * T.L.c8x8 -
-                    0.25 * T.L.c4x4 * rho2 < 0.0)
-                T.status |= IAT_ST_BOUND_SEEN;
-        }
-        if (rho_new < 0.01 * T.L.rm2) {   // separation below 0.1 r_m: integration broken
+    for (int k = 0; k < 6; ++k) {
+        W.d(k, i) = T.x[k];
+        W.d(6 + k, i) = T.v[k];
+    }
+    work_store_scal(W, i, T.S);
+}
+
+// One attempted step (or secant iterate) of a one-lane trajectory.
+__device__ __forceinline__ void traj1_advance(const KParams& P, Traj1& T)
+{
+    double h;
+    bool fin;
+    if (!step_prologue(P, T.S, h, fin)) return;
+    const bool exiting = T.S.mode != 0;
+    const double hh = h * h;
+    const StageCos C = stage_cos(T.S.tau, T.L.phase0, h);
+    double F2[6], F3[6], F4[6], F5[6], F6[6], X[6];
 #pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                T.x[k] = x5[k];
-                T.v[k] = v5[k];
-            }
-            T.tau = tau_new;
-            T.status |= IAT_ST_R_UNDERFLOW;
-            T.done = true;
-            return;
+    for (int k = 0; k < 6; ++k) X[k] = stage2(T.x[k], T.v[k], h);
+    accel1(P, T.L, C.c2, X, F2);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) X[k] = stage3(T.x[k], T.v[k], h, hh, T.F1[k]);
+    accel1(P, T.L, C.c3, X, F3);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) X[k] = stage4(T.x[k], T.v[k], h, hh, T.F1[k], F2[k]);
+    accel1(P, T.L, C.c4, X, F4);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) X[k] = stage5(T.x[k], T.v[k], h, hh, T.F1[k], F2[k], F3[k]);
+    accel1(P, T.L, C.c5, X, F5);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) X[k] = stage6(T.x[k], T.v[k], h, hh, T.F1[k], F2[k], F3[k], F4[k]);
+    accel1(P, T.L, C.c6, X, F6);
+    double x5[6], v5[6], ex[6], F7[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        x5[k] = sol_x(T.x[k], T.v[k], h, hh, T.F1[k], F2[k], F3[k], F4[k], F5[k]);
+        v5[k] = sol_v(T.v[k], h, T.F1[k], F3[k], F4[k], F5[k], F6[k]);
+        ex[k] = err_x(hh, T.F1[k], F2[k], F3[k], F4[k], F5[k], F6[k]);
+    }
+    double en = 0.0;
+    bool finite = true;
+    if (!exiting) {
+        accel1(P, T.L, C.c6, x5, F7);
+        bool bad = false;
+        double m = 0.0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const double ev = err_v(h, T.F1[k], F3[k], F4[k], F5[k], F6[k], F7[k]);
+            const double rx = err_ratio(ex[k], T.x[k], x5[k], P.rtol, P.atol);
+            const double rv = err_ratio(ev, T.v[k], v5[k], P.rtol, P.atol);
+            bad = bad || ratio_bad(rx) || ratio_bad(rv);
+            m = fmax(m, fmax(rx, rv));
+            finite = finite && is_finite(x5[k]) && is_finite(v5[k]);
         }
-        if (T.rho_prev <= P.r0sq && rho_new > P.r0sq && s_new > 0.0) {
-            // keep y_n; the next four calls are the secant iterates (x0, g0) -> (rho_prev, s_prev)
-            T.mode = 1;
-            T.s_prev = sqrt(T.rho_prev) - P.r0;
-            T.rho_prev = 0.0;
-            T.sx1 = h;
-            T.sg1 = sqrt(rho_new) - P.r0;
-            T.h = h;
-            return;
+        en = bad ? __builtin_nan("") : m;
+    }
+    const double d0 = x5[0] - x5[3], d1 = x5[1] - x5[4], d2 = x5[2] - x5[5];
+    const double w0 = v5[0] - v5[3], w1 = v5[1] - v5[4], w2 = v5[2] - v5[5];
+    const double rho_new = dot3(d0, d1, d2, d0, d1, d2);
+    const double s_new = dot3(d0, d1, d2, w0, w1, w2);
+    const double ww = dot3(w0, w1, w2, w0, w1, w2);
+    const StepOutcome o = step_epilogue(P, T.S, T.L, h, fin, en, finite, rho_new, s_new, ww);
+    if (o == OUT_SECANT_DONE || o == OUT_STOP_RFLOOR) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            T.x[k] = x5[k];
+            T.v[k] = v5[k];
         }
+    } else if (o == OUT_ACCEPT || o == OUT_TMAX) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             T.x[k] = x5[k];
             T.v[k] = v5[k];
             T.F1[k] = F7[k];
         }
-        T.tau = tau_new;
-        T.rho_prev = rho_new;
-        T.s_prev = s_new;
-        if (fin) {
-            T.status |= IAT_ST_TMAX;
-            T.done = true;
-            T.h = h;
-            return;
-        }
-        double fac = en == 0.0 ? 5.0 : fmin(5.0, fmax(0.2, 0.9 * exp2(-0.2 * log2(en))));
-        if (T.last_rej) fac = fmin(1.0, fac);
-        T.h = fmin(P.hmax, h * fac);
-        T.last_rej = false;
-    } else {
-        T.nrej++;
-        const double fac = (en != en) ? 0.2 : fmax(0.2, 0.9 * exp2(-0.2 * log2(en)));
-        T.h = h * fac;
-        T.last_rej = true;
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// Four lanes per trajectory: lane k = 0, 1, 2 of an aligned quad holds axis k (atom and ion
+// position, velocity and stage accelerations); lane 3 shadows axis 2.  Values shared across
+// axes (separation, radial rate, error norm) are gathered with quad DPP moves and evaluated
+// with the same expressions as the one-lane form, so both give the same bits.  Every branch
+// depends on quad-uniform values only, so the four lanes of a quad stay converged.
+// ---------------------------------------------------------------------------------------
+template <int SRC>
+__device__ __forceinline__ double quad_bcast(double v)
+{
+    constexpr int ctrl = SRC | (SRC << 2) | (SRC << 4) | (SRC << 6);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double quad_max(double v)
+{
+    constexpr int x1 = 1 | (0 << 2) | (3 << 4) | (2 << 6), x2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);
+    double o = __hiloint2double(__builtin_amdgcn_mov_dpp(__double2hiint(v), x1, 0xF, 0xF, false),
+                                __builtin_amdgcn_mov_dpp(__double2loint(v), x1, 0xF, 0xF, false));
+    v = fmax(v, o);
+    o = __hiloint2double(__builtin_amdgcn_mov_dpp(__double2hiint(v), x2, 0xF, 0xF, false),
+                         __builtin_amdgcn_mov_dpp(__double2loint(v), x2, 0xF, 0xF, false));
+    return fmax(v, o);
+}
+__device__ __forceinline__ int quad_or(int v)
+{
+    constexpr int x1 = 1 | (0 << 2) | (3 << 4) | (2 << 6), x2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);
+    v |= __builtin_amdgcn_mov_dpp(v, x1, 0xF, 0xF, false);
+    return v | __builtin_amdgcn_mov_dpp(v, x2, 0xF, 0xF, false);
+}
+
+struct Traj4 {
+    double xa, xi, va, vi, F1a, F1i;   // this lane's axis
+    Scal S;
+    Lane L;
+};
+
+__device__ __forceinline__ int quad_axis() { return min((int)(__lane_id() & 3), 2); }
+
+__device__ __forceinline__ void accel4(const KParams& P, const Lane& L, int k, double cs, double Xa, double Xi,
+                                       double& Aa, double& Ai)
+{
+    const double dk = Xa - Xi;
+    const double d0 = quad_bcast<0>(dk), d1 = quad_bcast<1>(dk), d2 = quad_bcast<2>(dk);
+    const double s = force_scale(L, d0, d1, d2);
+    const double qc = L.qx_half * cs;
+    const double kA = k == 0 ? P.kA[0] : (k == 1 ? P.kA[1] : P.kA[2]);
+    const double qr = k == 0 ? P.q_ratio[0] : (k == 1 ? P.q_ratio[1] : P.q_ratio[2]);
+    Aa = acc_atom(L, s, dk);
+    Ai = acc_ion(P.inv_mi, s, dk, kA, qc, qr, Xi);
+}
+
+__device__ __forceinline__ void traj4_advance(const KParams& P, Traj4& T)
+{
+    double h;
+    bool fin;
+    if (!step_prologue(P, T.S, h, fin)) return;
+    const bool exiting = T.S.mode != 0;
+    const int k = quad_axis();
+    const double hh = h * h;
+    const StageCos C = stage_cos(T.S.tau, T.L.phase0, h);
+    double F2a, F2i, F3a, F3i, F4a, F4i, F5a, F5i, F6a, F6i;
+    accel4(P, T.L, k, C.c2, stage2(T.xa, T.va, h), stage2(T.xi, T.vi, h), F2a, F2i);
+    accel4(P, T.L, k, C.c3, stage3(T.xa, T.va, h, hh, T.F1a), stage3(T.xi, T.vi, h, hh, T.F1i), F3a, F3i);
+    accel4(P, T.L, k, C.c4, stage4(T.xa, T.va, h, hh, T.F1a, F2a), stage4(T.xi, T.vi, h, hh, T.F1i, F2i), F4a,
+           F4i);
+    accel4(P, T.L, k, C.c5, stage5(T.xa, T.va, h, hh, T.F1a, F2a, F3a),
+           stage5(T.xi, T.vi, h, hh, T.F1i, F2i, F3i), F5a, F5i);
+    accel4(P, T.L, k, C.c6, stage6(T.xa, T.va, h, hh, T.F1a, F2a, F3a, F4a),
+           stage6(T.xi, T.vi, h, hh, T.F1i, F2i, F3i, F4i), F6a, F6i);
+    const double x5a = sol_x(T.xa, T.va, h, hh, T.F1a, F2a, F3a, F4a, F5a);
+    const double x5i = sol_x(T.xi, T.vi, h, hh, T.F1i, F2i, F3i, F4i, F5i);
+    const double v5a = sol_v(T.va, h, T.F1a, F3a, F4a, F5a, F6a);
+    const double v5i = sol_v(T.vi, h, T.F1i, F3i, F4i, F5i, F6i);
+    double en = 0.0, F7a = 0.0, F7i = 0.0;
+    bool finite = true;
+    if (!exiting) {
+        accel4(P, T.L, k, C.c6, x5a, x5i, F7a, F7i);
+        const double ra = err_ratio(err_x(hh, T.F1a, F2a, F3a, F4a, F5a, F6a), T.xa, x5a, P.rtol, P.atol);
+        const double ri = err_ratio(err_x(hh, T.F1i, F2i, F3i, F4i, F5i, F6i), T.xi, x5i, P.rtol, P.atol);
+        const double rva = err_ratio(err_v(h, T.F1a, F3a, F4a, F5a, F6a, F7a), T.va, v5a, P.rtol, P.atol);
+        const double rvi = err_ratio(err_v(h, T.F1i, F3i, F4i, F5i, F6i, F7i), T.vi, v5i, P.rtol, P.atol);
+        const int bad = quad_or((ratio_bad(ra) || ratio_bad(ri) || ratio_bad(rva) || ratio_bad(rvi)) ? 1 : 0);
+        const int nonfin =
+            quad_or((is_finite(x5a) && is_finite(x5i) && is_finite(v5a) && is_finite(v5i)) ? 0 : 1);
+        const double m = quad_max(fmax(fmax(ra, rva), fmax(ri, rvi)));
+        en = bad ? __builtin_nan("") : m;
+        finite = nonfin == 0;
+    }
+    const double dk = x5a - x5i, wk = v5a - v5i;
+    const double d0 = quad_bcast<0>(dk), d1 = quad_bcast<1>(dk), d2 = quad_bcast<2>(dk);
+    const double w0 = quad_bcast<0>(wk), w1 = quad_bcast<1>(wk), w2 = quad_bcast<2>(wk);
+    const double rho_new = dot3(d0, d1, d2, d0, d1, d2);
+    const double s_new = dot3(d0, d1, d2, w0, w1, w2);
+    const double ww = dot3(w0, w1, w2, w0, w1, w2);
+    const StepOutcome o = step_epilogue(P, T.S, T.L, h, fin, en, finite, rho_new, s_new, ww);
+    if (o == OUT_SECANT_DONE || o == OUT_STOP_RFLOOR) {
+        T.xa = x5a;
+        T.xi = x5i;
+        T.va = v5a;
+        T.vi = v5i;
+    } else if (o == OUT_ACCEPT || o == OUT_TMAX) {
+        T.xa = x5a;
+        T.xi = x5i;
+        T.va = v5a;
+        T.vi = v5i;
+        T.F1a = F7a;
+        T.F1i = F7i;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Outputs.
+// ---------------------------------------------------------------------------------------
 // Ion energy of Eq. (1) (kinetic + trap terms) in atomic units at internal time tau.
 __device__ __forceinline__ double ion_energy_au(const KParams& P, double qx, double phase0, const double y[12],
                                                 double tau)
@@ -566,21 +900,22 @@ __device__ __forceinline__ double ion_energy_au(const KParams& P, double qx, dou
     return 0.5 * P.m_ion * ke + pe * (P.m_ion * P.omega * P.omega / 8.0);
 }
 
-// Write the observables of trajectory i (outputs are in atomic units).
-__device__ inline void traj_finish(const KParams& P, int64_t i, const Traj& T)
+// Observables of trajectory i from its final state in the work buffer (outputs in a.u.).
+__device__ inline void work_observe(const KParams& P, const Work& W, int64_t i)
 {
     TrajParams tp;
     traj_params(P, i, tp);
     double y0[12];
     start_state_au(P, i, tp, y0);
     double yf[12];
-#pragma unroll
     for (int k = 0; k < 6; ++k) {
-        yf[k] = T.x[k];
-        yf[6 + k] = T.v[k] * P.omega;
+        yf[k] = W.d(k, i);
+        yf[6 + k] = W.d(6 + k, i) * P.omega;
     }
-    uint32_t st = T.status;
-    if (T.nb >= 2 || (st & IAT_ST_TMAX)) st |= IAT_ST_COMPLEX;
+    const double tau = W.d(19, i);
+    const int32_t nb = W.k(3, i);
+    uint32_t st = (uint32_t)W.k(4, i);
+    if (nb >= 2 || (st & IAT_ST_TMAX)) st |= IAT_ST_COMPLEX;
     const double* vi = y0 + 6;
     const double* vf = yf + 6;
     const double cx = vi[1] * vf[2] - vi[2] * vf[1];
@@ -590,20 +925,104 @@ __device__ inline void traj_finish(const KParams& P, int64_t i, const Traj& T)
     P.angle[i] = atan2(sqrt(cx * cx + cy * cy + cz * cz), dot);
     const double dv0 = vf[0] - vi[0], dv1 = vf[1] - vi[1], dv2 = vf[2] - vi[2];
     P.q_transfer[i] = species_mass(P, tp.sp) * sqrt(dv0 * dv0 + dv1 * dv1 + dv2 * dv2);
-    P.dE_ion[i] = ion_energy_au(P, tp.qx, tp.phase0, yf, T.tau) - ion_energy_au(P, tp.qx, tp.phase0, y0, 0.0);
+    P.dE_ion[i] = ion_energy_au(P, tp.qx, tp.phase0, yf, tau) - ion_energy_au(P, tp.qx, tp.phase0, y0, 0.0);
     const double inv_w = 1.0 / P.omega;
-    P.t_dwell[i] = T.tau * inv_w;
-    if (P.t_first) P.t_first[i] = T.tau_first * inv_w;
-    if (P.t_last) P.t_last[i] = T.tau_last * inv_w;
-    P.n_bounce[i] = T.nb;
+    P.t_dwell[i] = tau * inv_w;
+    if (P.t_first) P.t_first[i] = W.d(20, i) * inv_w;
+    if (P.t_last) P.t_last[i] = W.d(21, i) * inv_w;
+    P.n_bounce[i] = nb;
     P.status[i] = st;
-    if (P.n_accept) P.n_accept[i] = T.nacc;
-    if (P.n_reject) P.n_reject[i] = T.nrej;
-    if (P.n_rhs) P.n_rhs[i] = T.nrhs;
+    if (P.n_accept) P.n_accept[i] = W.k(0, i);
+    if (P.n_reject) P.n_reject[i] = W.k(1, i);
+    if (P.n_rhs) P.n_rhs[i] = W.k(2, i);
     if (P.y_final) {
-#pragma unroll
         for (int k = 0; k < 12; ++k) P.y_final[(int64_t)k * P.n + i] = yf[k];
     }
+}
+
+// ---------------------------------------------------------------------------------------
+// Suspended trajectories (continuation records), structure of arrays of capacity cap:
+// doubles [26][cap]: x[6], v[6], F1[6], tau, h, rho_prev, s_prev, sx1, sg1, tau_first, tau_last;
+// int32 [8][cap]: nacc, nrej, nrhs, nb, status, mode, last_rej, (pad); int64 [cap]: id.
+// ---------------------------------------------------------------------------------------
+struct Cont {
+    double* d;
+    int32_t* n;
+    int64_t* id;
+    int64_t cap;
+    unsigned long long* count;   // records written
+    unsigned long long* head;    // records taken by the resuming kernel
+};
+
+__device__ inline void cont_save(const Cont& C, int64_t slot, int64_t i, const Traj1& T)
+{
+    const int64_t c = C.cap;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        C.d[(0 + k) * c + slot] = T.x[k];
+        C.d[(6 + k) * c + slot] = T.v[k];
+        C.d[(12 + k) * c + slot] = T.F1[k];
+    }
+    const Scal& S = T.S;
+    C.d[18 * c + slot] = S.tau;
+    C.d[19 * c + slot] = S.h;
+    C.d[20 * c + slot] = S.rho_prev;
+    C.d[21 * c + slot] = S.s_prev;
+    C.d[22 * c + slot] = S.sx1;
+    C.d[23 * c + slot] = S.sg1;
+    C.d[24 * c + slot] = S.tau_first;
+    C.d[25 * c + slot] = S.tau_last;
+    C.n[0 * c + slot] = S.nacc;
+    C.n[1 * c + slot] = S.nrej;
+    C.n[2 * c + slot] = S.nrhs;
+    C.n[3 * c + slot] = S.nb;
+    C.n[4 * c + slot] = (int32_t)S.status;
+    C.n[5 * c + slot] = (int32_t)S.mode;
+    C.n[6 * c + slot] = S.last_rej;
+    C.id[slot] = i;
+}
+
+__device__ inline void cont_load4(const KParams& P, const Work& W, const Cont& C, int64_t slot, int k, Traj4& T,
+                                  int64_t& i)
+{
+    const int64_t c = C.cap;
+    i = C.id[slot];
+    (void)P;
+    T.xa = C.d[(0 + k) * c + slot];
+    T.xi = C.d[(3 + k) * c + slot];
+    T.va = C.d[(6 + k) * c + slot];
+    T.vi = C.d[(9 + k) * c + slot];
+    T.F1a = C.d[(12 + k) * c + slot];
+    T.F1i = C.d[(15 + k) * c + slot];
+    Scal& S = T.S;
+    S.tau = C.d[18 * c + slot];
+    S.h = C.d[19 * c + slot];
+    S.rho_prev = C.d[20 * c + slot];
+    S.s_prev = C.d[21 * c + slot];
+    S.sx1 = C.d[22 * c + slot];
+    S.sg1 = C.d[23 * c + slot];
+    S.tau_first = C.d[24 * c + slot];
+    S.tau_last = C.d[25 * c + slot];
+    S.nacc = C.n[0 * c + slot];
+    S.nrej = C.n[1 * c + slot];
+    S.nrhs = C.n[2 * c + slot];
+    S.nb = C.n[3 * c + slot];
+    S.status = (uint32_t)C.n[4 * c + slot];
+    S.mode = (uint32_t)C.n[5 * c + slot];
+    S.last_rej = C.n[6 * c + slot];
+    S.done = 0;
+    work_lane(W, i, T.L);
+}
+
+__device__ __forceinline__ void traj4_store(const Work& W, int64_t i, const Traj4& T, int lane_in_quad)
+{
+    if (lane_in_quad < 3) {
+        W.d(lane_in_quad, i) = T.xa;
+        W.d(3 + lane_in_quad, i) = T.xi;
+        W.d(6 + lane_in_quad, i) = T.va;
+        W.d(9 + lane_in_quad, i) = T.vi;
+    }
+    if (lane_in_quad == 0) work_store_scal(W, i, T.S);
 }
 
 }  // namespace iat

@@ -17,7 +17,12 @@
 #include "iat_device.h"
 #include "iat_host.h"
 
+#include <algorithm>
+
 namespace iat {
+
+constexpr int64_t kDefaultBudget = 20000;        // attempted steps before a trajectory moves to 4 lanes
+constexpr int64_t kMaxSuspended = 1 << 21;       // continuation records per call
 
 __device__ __forceinline__ uint64_t wave_sum(uint64_t v)
 {
@@ -54,38 +59,53 @@ __device__ __forceinline__ void flush_stats(uint64_t* stats, const LaneStats& s,
     }
 }
 
-__global__ void __launch_bounds__(256) k_integrate_plain(KParams P)
+__global__ void __launch_bounds__(256) k_setup(KParams P, Work W)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < P.n) work_setup(P, W, i);
+}
+
+__global__ void __launch_bounds__(256) k_observe(KParams P, Work W)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < P.n) work_observe(P, W, i);
+}
+
+__global__ void __launch_bounds__(256) k_integrate_plain(KParams P, Work W)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     LaneStats st;
     uint64_t iters = 0;
     if (i < P.n) {
-        Traj T;
-        traj_start(P, i, T);
-        while (!T.done) {
-            traj_advance(P, T);
+        Traj1 T;
+        traj1_start(P, W, i, T);
+        while (!T.S.done) {
+            traj1_advance(P, T);
             ++iters;
         }
-        traj_finish(P, i, T);
-        st.rhs = T.nrhs;
-        st.acc = T.nacc;
-        st.rej = T.nrej;
+        traj1_store(W, i, T);
+        st.rhs = T.S.nrhs;
+        st.acc = T.S.nacc;
+        st.rej = T.S.nrej;
         st.done = 1;
-        st.useful = T.nacc + T.nrej;
+        st.useful = T.S.nacc + T.S.nrej;
     }
     // every lane of the wave is issued for as many steps as its slowest lane needed
     flush_stats(P.stats, st, 64ull * wave_max(iters));
 }
 
-__global__ void __launch_bounds__(256) k_integrate_persistent(KParams P, unsigned long long* queue)
+// Persistent refill kernel.  A trajectory that has used `budget` attempted steps without
+// finishing is suspended into the continuation records (while slots last) and its lane takes
+// new work; k_integrate_tail finishes the suspended ones four lanes per trajectory.
+__global__ void __launch_bounds__(256) k_integrate_persistent(KParams P, Work W, unsigned long long* queue, Cont C)
 {
     const int lane = __lane_id();
     const uint64_t lanemask_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     LaneStats st;
     uint64_t iters = 0;
-    Traj T;
+    Traj1 T;
     int64_t i = -1;
-    bool active = false, need = true;
+    bool active = false, need = true, may_suspend = P.budget > 0;
     for (;;) {
         // hand out new ids to the lanes that need one: one atomic per wave
         const uint64_t mask = __ballot(need);
@@ -97,30 +117,100 @@ __global__ void __launch_bounds__(256) k_integrate_persistent(KParams P, unsigne
             if (need) {
                 i = (int64_t)(base + __popcll(mask & lanemask_lt));
                 active = i < P.n;
-                if (active) traj_start(P, i, T);
+                if (active) traj1_start(P, W, i, T);
                 need = false;
             }
         }
         if (!__any(active)) break;
         for (int k = 0; k < P.refill_every; ++k) {
-            if (active && !T.done) traj_advance(P, T);
+            if (active && !T.S.done) traj1_advance(P, T);
         }
         iters += P.refill_every;
-        if (active && T.done) {
-            traj_finish(P, i, T);
-            st.rhs += T.nrhs;
-            st.acc += T.nacc;
-            st.rej += T.nrej;
-            st.done += 1;
-            st.useful += T.nacc + T.nrej;
-            active = false;
-            need = true;
+        if (active) {
+            if (T.S.done) {
+                traj1_store(W, i, T);
+                st.rhs += T.S.nrhs;
+                st.acc += T.S.nacc;
+                st.rej += T.S.nrej;
+                st.done += 1;
+                st.useful += T.S.nacc + T.S.nrej;
+                active = false;
+                need = true;
+            } else if (may_suspend && T.S.nacc + T.S.nrej >= P.budget) {
+                const unsigned long long slot = atomicAdd(C.count, 1ull);
+                if ((int64_t)slot < C.cap) {
+                    cont_save(C, (int64_t)slot, i, T);
+                    st.useful += T.S.nacc + T.S.nrej;
+                    active = false;
+                    need = true;
+                } else {
+                    may_suspend = false;
+                }
+            }
         }
     }
     flush_stats(P.stats, st, 64ull * iters);
 }
 
-__global__ void k_reset_counter(unsigned long long* q) { *q = 0ull; }
+// Finishes suspended trajectories with four lanes each (one per axis): the per-step latency of
+// a long-lived complex is what bounds a batch's wall time.
+__global__ void __launch_bounds__(256) k_integrate_tail(KParams P, Work W, Cont C)
+{
+    const int lane = __lane_id();
+    const int qlead = lane & ~3;
+    const bool leader = (lane & 3) == 0;
+    const uint64_t lt = (qlead == 0) ? 0ull : (~0ull >> (64 - qlead));
+    const int k = quad_axis();
+    unsigned long long cnt = *C.count;
+    const int64_t total = (int64_t)(cnt < (unsigned long long)C.cap ? cnt : (unsigned long long)C.cap);
+    LaneStats st;
+    uint64_t iters = 0;
+    Traj4 T;
+    int64_t i = -1;
+    int32_t resumed_at = 0;
+    bool active = false, need = true;
+    for (;;) {
+        const uint64_t mask = __ballot(need && leader);
+        if (mask) {
+            const int first = __ffsll((unsigned long long)mask) - 1;
+            unsigned long long base = 0;
+            if (lane == first) base = atomicAdd(C.head, (unsigned long long)__popcll(mask));
+            base = __shfl(base, first, 64);
+            if (need) {
+                const int64_t slot = (int64_t)(base + __popcll(mask & lt));
+                active = slot < total;
+                if (active) {
+                    cont_load4(P, W, C, slot, k, T, i);
+                    resumed_at = T.S.nacc + T.S.nrej;
+                }
+                need = false;
+            }
+        }
+        if (!__any(active)) break;
+        if (active && !T.S.done) traj4_advance(P, T);
+        ++iters;
+        if (active && T.S.done) {
+            traj4_store(W, i, T, lane & 3);
+            if (leader) {
+                st.rhs += T.S.nrhs;
+                st.acc += T.S.nacc;
+                st.rej += T.S.nrej;
+                st.done += 1;
+                st.useful += T.S.nacc + T.S.nrej - resumed_at;
+            }
+            active = false;
+            need = true;
+        }
+    }
+    // a wave carries 16 trajectories: 16 step slots per iteration
+    flush_stats(P.stats, st, 0ull);
+    if (P.stats && lane == 0) atomicAdd((unsigned long long*)&P.stats[4], (unsigned long long)(16ull * iters));
+}
+
+__global__ void k_reset_counters(unsigned long long* q, int n)
+{
+    if ((int)threadIdx.x < n) q[threadIdx.x] = 0ull;
+}
 
 }  // namespace iat
 
@@ -142,46 +232,26 @@ const char* last_error() { return g_err; }
 
 namespace {
 constexpr int kMaxDevices = 64;
-constexpr int kQueueSlots = 256;
-struct DeviceState {
-    unsigned long long* queues = nullptr;
-    std::atomic<unsigned> next{0};
-    int n_cu = 0;
-};
-DeviceState g_dev[kMaxDevices];
+int g_n_cu[kMaxDevices];
 std::mutex g_mu;
 }  // namespace
 
-int device_state(int* n_cu, unsigned long long** queue_slot)
+// Compute-unit count of the current device (cached).
+int device_state(int* n_cu, unsigned long long** unused)
 {
+    (void)unused;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
         return set_error(IAT_EHIP, "hipGetDevice failed");
-    DeviceState& d = g_dev[dev];
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        if (!d.queues) {
-            void* p = nullptr;
-            if (hipMalloc(&p, sizeof(unsigned long long) * kQueueSlots) != hipSuccess)
-                return set_error(IAT_EHIP, "hipMalloc of the work-queue counters failed");
-            d.queues = (unsigned long long*)p;
-            if (hipDeviceGetAttribute(&d.n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-                return set_error(IAT_EHIP, "hipDeviceGetAttribute failed");
-        }
-    }
-    if (n_cu) *n_cu = d.n_cu;
-    if (queue_slot) *queue_slot = d.queues + (d.next.fetch_add(1) % kQueueSlots);
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_n_cu[dev] == 0 &&
+        hipDeviceGetAttribute(&g_n_cu[dev], hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return set_error(IAT_EHIP, "hipDeviceGetAttribute failed");
+    if (n_cu) *n_cu = g_n_cu[dev];
     return 0;
 }
 
-void release_devices()
-{
-    std::lock_guard<std::mutex> lk(g_mu);
-    for (auto& d : g_dev) {
-        if (d.queues) (void)hipFree(d.queues);
-        d.queues = nullptr;
-    }
-}
+void release_devices() {}
 
 static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
@@ -199,6 +269,8 @@ int validate_common(const iat_system* sys, const iat_species* species, int n_spe
     if (!finite_pos(sys->rtol) || !finite_pos(sys->atol)) return set_error(IAT_EINVAL, "rtol and atol must be > 0");
     if (sys->h0 < 0 || sys->hmax < 0 || sys->hmin < 0 || sys->r_bounce_over_rm < 0 || sys->max_steps < 0)
         return set_error(IAT_EINVAL, "h0, hmax, hmin, r_bounce_over_rm and max_steps must be >= 0");
+    if (sys->t_max * sys->omega_rf + std::fabs(sys->phase0) > 1.5e6)
+        return set_error(IAT_EINVAL, "Omega t_max must stay below 1.5e6 RF radians (phase reduction range)");
     if (sys->hmax > kTwoPi / 8.0)
         return set_error(IAT_EINVAL, "hmax must not exceed pi/4 (an eighth of the RF period in tau units)");
     if (!std::isfinite(sys->a_x) || !std::isfinite(sys->q_x) || !std::isfinite(sys->phase0))
@@ -323,6 +395,7 @@ int resolve_launch(const iat_launch* launch, iat_launch* out)
     if (L.refill_every == 0) L.refill_every = 1;
     if (L.refill_every < 1 || L.refill_every > 4096)
         return set_error(IAT_EINVAL, "launch.refill_every must be in [1, 4096]");
+    if (L.step_budget < -1) return set_error(IAT_EINVAL, "launch.step_budget must be >= -1");
     *out = L;
     return 0;
 }
@@ -353,15 +426,41 @@ extern "C" int iat_integrate(const iat_system* sys, const iat_species* species, 
     P.stats = L.stats;
     P.refill_every = L.refill_every;
     hipStream_t st = (hipStream_t)stream;
+    int n_cu = 0;
+    rc = device_state(&n_cu, nullptr);
+    if (rc) return rc;
+    const int64_t n = batch->n;
+    if (n > (int64_t)0x7fffffff * 256) return set_error(IAT_EINVAL, "batch too large for one launch");
+    const unsigned nblk = (unsigned)((n + 255) / 256);
+    P.budget = 0;
+    int64_t cap = 0;
+    if (L.kernel == IAT_KERNEL_PERSISTENT) {
+        P.budget = L.step_budget > 0 ? L.step_budget : (L.step_budget == 0 ? kDefaultBudget : 0);
+        cap = P.budget > 0 ? std::min<int64_t>(n, kMaxSuspended) : 0;
+    }
+    // one stream-ordered block: queue counters | work buffer | continuation records
+    const size_t rec = 26 * sizeof(double) + 8 * sizeof(int32_t) + sizeof(int64_t);
+    const size_t work_bytes = (size_t)n * (kWorkDoubles * sizeof(double) + kWorkInts * sizeof(int32_t));
+    const size_t bytes = 256 + ((work_bytes + 255) / 256) * 256 + (size_t)cap * rec;
+    void* ws = nullptr;
+    if (hipMallocAsync(&ws, bytes, st) != hipSuccess) return set_error(IAT_EHIP, "hipMallocAsync of %zu bytes failed", bytes);
+    unsigned long long* q = (unsigned long long*)ws;
+    Work W;
+    W.n = n;
+    W.D = (double*)((char*)ws + 256);
+    W.I = (int32_t*)(W.D + (size_t)kWorkDoubles * n);
+    Cont C;
+    C.count = q + 1;
+    C.head = q + 2;
+    C.cap = cap;
+    C.d = (double*)((char*)ws + 256 + ((work_bytes + 255) / 256) * 256);
+    C.n = (int32_t*)(C.d + 26 * cap);
+    C.id = (int64_t*)(C.n + 8 * cap);
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, st, q, 4);
+    hipLaunchKernelGGL(k_setup, dim3(nblk), dim3(256), 0, st, P, W);
     if (L.kernel == IAT_KERNEL_PLAIN) {
-        const int64_t blocks = (batch->n + L.block - 1) / L.block;
-        if (blocks > 0x7fffffffLL) return set_error(IAT_EINVAL, "batch too large for one launch");
-        hipLaunchKernelGGL(k_integrate_plain, dim3((unsigned)blocks), dim3(L.block), 0, st, P);
+        hipLaunchKernelGGL(k_integrate_plain, dim3((unsigned)((n + L.block - 1) / L.block)), dim3(L.block), 0, st, P, W);
     } else {
-        int n_cu = 0;
-        unsigned long long* q = nullptr;
-        rc = device_state(&n_cu, &q);
-        if (rc) return rc;
         int per_cu = L.blocks_per_cu;
         if (per_cu == 0) {
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_integrate_persistent, L.block,
@@ -369,11 +468,22 @@ extern "C" int iat_integrate(const iat_system* sys, const iat_species* species, 
                 per_cu = 1;
         }
         int64_t blocks = (int64_t)n_cu * per_cu;
-        const int64_t need = (batch->n + L.block - 1) / L.block;
+        const int64_t need = (n + L.block - 1) / L.block;
         if (blocks > need) blocks = need;
-        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, q);
-        hipLaunchKernelGGL(k_integrate_persistent, dim3((unsigned)blocks), dim3(L.block), 0, st, P, q);
+        hipLaunchKernelGGL(k_integrate_persistent, dim3((unsigned)blocks), dim3(L.block), 0, st, P, W, q, C);
+        if (cap > 0) {
+            int per_cu4 = 1;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu4, (const void*)k_integrate_tail, 256, 0) !=
+                    hipSuccess || per_cu4 < 1)
+                per_cu4 = 1;
+            int64_t blocks4 = (int64_t)n_cu * per_cu4;
+            const int64_t need4 = (4 * cap + 255) / 256;
+            if (blocks4 > need4) blocks4 = need4;
+            hipLaunchKernelGGL(k_integrate_tail, dim3((unsigned)blocks4), dim3(256), 0, st, P, W, C);
+        }
     }
+    hipLaunchKernelGGL(k_observe, dim3(nblk), dim3(256), 0, st, P, W);
+    if (hipFreeAsync(ws, st) != hipSuccess) return set_error(IAT_EHIP, "hipFreeAsync failed");
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(IAT_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
     return 0;

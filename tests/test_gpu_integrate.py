@@ -68,9 +68,12 @@ def test_sweep_parity_ragged(kernel):
 
 
 def test_plain_and_persistent_are_bitwise_identical():
-    for w, n in ((W.config1(), 64), (W.config3(), 3000)):
+    """Same ids -> same bits, whichever kernel, lane or launch shape; a small step budget sends
+    most trajectories through the four-lanes-per-trajectory kernel, so it is checked too."""
+    for w, n in ((W.config1(), 64), (W.config3(), 3001)):
         a = run(w, n=n, kernel="plain")
-        for kw in (dict(block=256), dict(block=64, refill_every=4), dict(block=128, blocks_per_cu=1)):
+        for kw in (dict(block=256), dict(block=64, refill_every=4), dict(block=128, blocks_per_cu=1),
+                   dict(step_budget=-1), dict(step_budget=7), dict(step_budget=500, refill_every=3)):
             b = run(w, n=n, kernel="persistent", **kw)
             for k in a:
                 assert np.array_equal(a[k], b[k], equal_nan=True), (w.name, kw, k)

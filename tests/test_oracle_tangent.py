@@ -1,0 +1,77 @@
+"""Pins of the oracle's tangent-linear (internal differentiation of the accepted-step map).
+
+* The stability matrix of a Hamiltonian flow is symplectic: Phi^T Omega Phi = Omega with the
+  mass-weighted form Omega = [[0, M], [-M, 0]] of the (r, v) coordinates.  Every entry of the
+  Jacobian (the force Hessian, mass factors, signs, the trap term) enters this identity.
+* Observable sensitivities agree with frozen-step central differences of the oracle's own
+  primal, entry by entry at the best of several steps.
+* At the step h = 1e-6 relative, central differences agree in the norm of the
+  parameter-scaled gradient only to a few 1e-3: the frozen-step map is strongly nonlinear in E
+  (the recorded fine steps around the bounce stop fitting a trajectory whose bounce moves), so
+  the difference quotient itself is off by O(h^2) = 2e-4 there; it falls to 2e-6 at h = 1e-7.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+oracle.build()
+
+DIRECT_IDS = [40, 47, 51, 58, 63]      # one-bounce cells of the 8x8 grid
+
+
+def _problem(gid, rtol=1e-10):
+    w = W.config1()
+    w.system.rtol = rtol
+    p = oracle.problems_for(w, [gid])[0]
+    th, ph = oracle.grid_angles([gid], 8, 8)[0]
+    return w, p, th, ph
+
+
+def _scales(w):
+    return np.array([1.0, 1.0, w.system.E, w.system.q_x, w.system.De])
+
+
+@pytest.mark.parametrize("gid", DIRECT_IDS[:3])
+def test_stability_matrix_is_symplectic(gid):
+    w, p, th, ph = _problem(gid)
+    _, Phi, _ = oracle.tangent(p, th, ph, w.system.E, w.system.q_ratio)
+    M = np.diag([p["m_atom"]] * 3 + [p["m_ion"]] * 3)
+    Om = np.block([[np.zeros((6, 6)), M], [-M, np.zeros((6, 6))]])
+    defect = Phi.T @ Om @ Phi - Om
+    scale = np.abs(Phi.T) @ np.abs(Om) @ np.abs(Phi)
+    assert (np.abs(defect) / scale).max() < 1e-7
+    # and it is not trivially so: the collision stretches phase space by orders of magnitude
+    assert np.linalg.svd(Phi, compute_uv=False)[0] > 100.0
+
+
+@pytest.mark.parametrize("gid", DIRECT_IDS)
+def test_sensitivities_match_central_differences_entrywise(gid):
+    """Each sizeable entry (>= 1% of the observable's largest parameter-scaled sensitivity)
+    agrees to 1e-3 at the best of several difference steps (the differences themselves resolve
+    some entries only to a few 1e-4).  Frozen steps limit the usable
+    step from above (the recorded fine steps around the bounce stop fitting a perturbed
+    trajectory) and round-off limits it from below, so the error curve has a minimum."""
+    w, p, th, ph = _problem(gid)
+    d, _, _ = oracle.tangent(p, th, ph, w.system.E, w.system.q_ratio)
+    fds = [oracle.fd(p, th, ph, w.system.E, w.system.q_ratio, rh) for rh in (1e-5, 3e-6, 1e-6, 3e-7, 1e-7)]
+    s = _scales(w)
+    for k in range(3):
+        g = d[k] * s
+        big = np.abs(g) >= 0.01 * np.abs(g).max()
+        best = np.min([np.abs(g - f[k] * s) for f in fds], axis=0)
+        assert np.all(best[big] <= 1e-3 * np.abs(g[big])), (k, g, best)
+    # the azimuthal derivative vanishes for the axially symmetric trap
+    assert np.all(np.abs(d[:, 1] * s[1]) < 1e-6 * np.abs(d * s).max(axis=1))
+
+
+@pytest.mark.parametrize("gid", DIRECT_IDS[:2])
+def test_sensitivities_match_central_differences_at_1e_6(gid):
+    w, p, th, ph = _problem(gid)
+    d, _, _ = oracle.tangent(p, th, ph, w.system.E, w.system.q_ratio)
+    f = oracle.fd(p, th, ph, w.system.E, w.system.q_ratio, 1e-6)
+    s = _scales(w)
+    for k in range(3):
+        g, gf = d[k] * s, f[k] * s
+        assert np.linalg.norm(g - gf) < 5e-3 * np.linalg.norm(gf)
