@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (counter calibration) and exit")
     return ap.parse_args()
 
 
@@ -52,7 +54,10 @@ def workload(name):
 
 
 def timed_runs(api, torch, w, out, stats, steps, warmup, **launch):
-    """Warm up, then time `steps` full passes with HIP events on the launch stream."""
+    """Warm up, then time `steps` full passes with HIP events on the launch stream.  Each pass also
+    reports its phase durations (setup, main kernel, tail kernel, observables), which the library
+    measures with HIP events recorded on the same stream between its kernels."""
+    import ctypes
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         api.integrate_workload(w, out=out, **launch)
@@ -60,24 +65,23 @@ def timed_runs(api, torch, w, out, stats, steps, warmup, **launch):
     stats.zero_()
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    per = []
+    phases = []
     t0 = time.perf_counter()
     ev0.record(stream)
-    for _ in range(steps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        api.integrate_workload(w, out=out, stats=stats, **launch)
-        e1.record(stream)
-        per.append((e0, e1))
-        print(f"[bench] launched pass {len(per)}/{steps} ({launch.get('kernel')})", file=sys.stderr, flush=True)
+    for k in range(steps):
+        ms = (ctypes.c_float * 4)()
+        api.integrate_workload(w, out=out, stats=stats, kernel_ms=ms, **launch)
+        phases.append(list(ms))
+        print(f"[bench] pass {k + 1}/{steps} ({launch.get('kernel')}): phases ms "
+              f"{[round(x, 3) for x in ms]}", file=sys.stderr, flush=True)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     total_ms = ev0.elapsed_time(ev1)
-    launch_ms = [a.elapsed_time(b) for a, b in per]
     s = stats.cpu().tolist()
-    return dict(total_s=total_ms / 1e3, wall_s=wall, launch_ms=launch_ms, rhs=s[0], acc=s[1], rej=s[2],
-                done=s[3], issued=s[4], useful=s[5])
+    avg = [sum(p[j] for p in phases) / len(phases) for j in range(4)]
+    return dict(total_s=total_ms / 1e3, wall_s=wall, phase_ms=avg, rhs=s[0], acc=s[1], rej=s[2],
+                done=s[3], issued=s[4], useful=s[5], tail_rhs=s[6], tail_done=s[7])
 
 
 def cpu_baseline(w, target_s):
@@ -85,13 +89,18 @@ def cpu_baseline(w, target_s):
     import numpy as np
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    # calibrate on a small sample, then size the sample to ~target_s of wall time
-    n_cal = 64
-    ids = np.linspace(0, w.n - 1, n_cal).astype(np.int64)
-    t = time.perf_counter()
-    oracle.integrate(oracle.problems_for(w, ids), threads)
-    dt = max(time.perf_counter() - t, 1e-3)
-    n = int(min(max(n_cal, n_cal * target_s / dt), 200_000, w.n))
+    # size the sample to ~target_s of wall time: grow a calibration sample until it takes a second
+    # (small samples are dominated by their longest trajectory), then scale
+    n_cal = 256
+    while True:
+        ids = np.linspace(0, w.n - 1, n_cal).astype(np.int64)
+        t = time.perf_counter()
+        oracle.integrate(oracle.problems_for(w, ids), threads)
+        dt = max(time.perf_counter() - t, 1e-3)
+        if dt >= 1.0 or n_cal >= w.n or n_cal * 4 * 1.0 / dt > 400_000:
+            break
+        n_cal *= 4
+    n = int(min(max(n_cal, n_cal * target_s / dt), 400_000, w.n))
     ids = np.linspace(0, w.n - 1, n).astype(np.int64)
     P = oracle.problems_for(w, ids)
     t = time.perf_counter()
@@ -102,8 +111,48 @@ def cpu_baseline(w, target_s):
                 rk_stages_per_s=float(R["n_rhs"].sum()) / el)
 
 
+def sources_digest():
+    """sha256 over the library's HIP sources and headers (names which build the counters were taken on)."""
+    import hashlib
+    h = hashlib.sha256()
+    for d in (os.path.join(ROOT, "paper_2509_15117_amd", "csrc"), os.path.join(ROOT, "include")):
+        for f in sorted(os.listdir(d)):
+            if f.endswith((".hip", ".h")):
+                h.update(f.encode())
+                h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
+def traffic_bytes(path, workload_name, kernel):
+    """HBM bytes per launch of `kernel` from PMC runs (FETCH_SIZE + WRITE_SIZE, scaled by a copy-kernel
+    calibration), or None when absent or taken on other sources."""
+    try:
+        tr = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if tr.get("workload") != workload_name or tr.get("kernel") != kernel or tr.get("sources") != sources_digest():
+        return None
+    return tr.get("bytes_per_launch")
+
+
+def calibrate_copy(nbytes, reps):
+    """A plain device-to-device copy of known size: the reference for the PMC byte counters."""
+    import torch
+    torch.cuda.set_device(0)
+    n = nbytes // 8
+    a = torch.arange(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "reps": reps}), flush=True)
+
+
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy, 3)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -123,17 +172,14 @@ def main():
     K = args.steps
     traj_s = w.n * K / r["total_s"]
     stages_s = r["rhs"] / r["total_s"]
-    avg_launch_s = sum(r["launch_ms"]) / len(r["launch_ms"]) / 1e3
-    flop_per_launch = FLOP_PER_RHS * r["rhs"] / K
-    achieved = flop_per_launch / avg_launch_s / 1e12
-    traffic = None
-    if os.path.exists(args.traffic_file):
-        try:
-            tr = json.load(open(args.traffic_file))
-            if tr.get("workload") == w.name and tr.get("kernel") == args.kernel:
-                traffic = tr.get("bytes_per_launch")
-        except (OSError, ValueError):
-            traffic = None
+    # dominant kernel: the main integration kernel (persistent or plain); its algorithmic FLOP are
+    # those of the RHS evaluations it performed (all of them minus the tail kernel's)
+    main_name = "k_integrate_persistent" if args.kernel == "persistent" else "k_integrate_plain"
+    main_s = r["phase_ms"][1] / 1e3
+    main_rhs = (r["rhs"] - r["tail_rhs"]) / K
+    achieved = FLOP_PER_RHS * main_rhs / main_s / 1e12
+    tail_s = r["phase_ms"][2] / 1e3
+    traffic = traffic_bytes(args.traffic_file, w.name, main_name)
     res = {
         "metric": "trajectories/s + RK stages/s (FP64, rtol 1e-10): refill kernel vs plain, % FP64 peak",
         "value": traj_s,
@@ -153,8 +199,13 @@ def main():
         "accepted_steps_per_s": r["acc"] / r["total_s"],
         "fp64_frac_peak": FLOP_PER_RHS * stages_s / (FP64_PEAK_TFLOPS * 1e12),
         "active_lane_fraction": r["useful"] / max(r["issued"], 1),
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic},
+        "roofline": {"bound": "alu", "kernel": main_name, "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
+                     "avg_launch_ms": main_s * 1e3, "flop_per_launch": FLOP_PER_RHS * main_rhs},
+        "phases_ms": {"setup": r["phase_ms"][0], "main": r["phase_ms"][1], "tail": r["phase_ms"][2],
+                      "observe": r["phase_ms"][3]},
+        "tail": {"kernel": "k_integrate_tail", "trajectories": r["tail_done"] / K, "rhs": r["tail_rhs"] / K,
+                 "achieved_tflops": FLOP_PER_RHS * r["tail_rhs"] / K / tail_s / 1e12 if tail_s > 0 else None},
     }
     if not args.no_plain and args.kernel != "plain":
         rp = timed_runs(api, torch, w, out, stats, 1, 0, **dict(launch, kernel="plain"))

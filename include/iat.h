@@ -146,7 +146,11 @@ enum { IAT_KERNEL_PLAIN = 1, IAT_KERNEL_PERSISTENT = 2 };
  * Zero fields take defaults.  stats, if not NULL, is a device uint64[8] to which the
  * call ADDS: [0] RHS evaluations, [1] accepted steps, [2] rejected steps,
  * [3] trajectories finished, [4] issued lane-steps (wave iterations x 64),
- * [5] useful lane-steps (attempted steps). */
+ * [5] useful lane-steps (attempted steps), [6] RHS evaluations performed inside the
+ * four-lane tail kernel, [7] trajectories finished by the tail kernel.
+ * kernel_ms, if not NULL, is HOST float[4] that receives the durations of the call's phases on
+ * its stream (setup, main integration kernel, tail kernel, observables), measured with HIP
+ * events; the call then waits for its work to finish before returning. */
 typedef struct {
     int32_t kernel;
     int32_t block;            /* threads per block: 64, 128, 192 or 256                */
@@ -156,8 +160,9 @@ typedef struct {
                                  trajectory is suspended and finished by four lanes (one
                                  per axis) to cut the latency of long-lived complexes;
                                  0 = default (20000), -1 = never                         */
-    int32_t reserved[3];
+    int32_t reserved;
     uint64_t* stats;
+    float* kernel_ms;
 } iat_launch;
 
 /* Integrate a batch (the paper's head-on runs: model paragraph, head-on-run paragraph,
@@ -167,17 +172,23 @@ int iat_integrate(const iat_system* sys, const iat_species* species /* host */, 
                   const iat_batch* batch, const iat_obs* obs, const iat_launch* launch,
                   void* ckpt_ws, size_t ckpt_bytes, void* stream);
 
-/* Reductions of a batch's outputs (the ensemble quantities of Figs. 3 and 4).
- * kind IAT_REDUCE_CELLS: per cell c of the SWEEP generator (cell = id mod n_cells), out is
- *   double[n_cells * 5] = (count, complex count, sum dE_ion, sum dE_ion^2, sum n_bounce).
- * kind IAT_REDUCE_W0_HIST: per species s, 64 bins of log10(E/W0) over [-3, 3] (clamped),
- *   W0 from Eq. (2) with omega = (Omega/2) sqrt(a_x + q_x^2/2); out is double[n_species*64*2]
- *   = (total, complex) counts; then 256 bins of the ion heating
- *   sign(dE) log10(1 + |dE|/(k_B 1 nK)) over +-log10(1 + 1e8) (clamped): double[256].
- * Sums are accumulated in a fixed order, so results do not depend on scheduling.
- * out is device memory that the call ADDS to (zero it first to start). */
+/* Reductions of a batch's outputs (the ensemble quantities of Figs. 3 and 4, and the fractal
+ * structure of Fig. 1).  obs needs dE_ion, n_bounce and status.  out is device memory; CELLS and W0_HIST
+ * ADD to it (zero it first to start), so chunks of one sweep accumulate; BOXCOUNT overwrites it.
+ * IAT_REDUCE_CELLS (SWEEP batches): per cell c (cell = id mod n_cells), out[5c..5c+4] =
+ *   (count, complex count, sum dE_ion, sum dE_ion^2, sum n_bounce); sums run in a fixed order.
+ * IAT_REDUCE_W0_HIST: per species slot s of the sweep list (slot 0 otherwise), 64 bins of
+ *   log10(E/W0) over [-3, 3] (clamped), out[(s*64 + b)*2 + {0,1}] = (total, complex) counts, W0 from
+ *   Eq. (2) with omega = (Omega/2) sqrt(a_x + q_x^2/2); then out[n_slots*128 + b], b < 256: counts of
+ *   sign(dE) log10(1 + |dE|/(k_B 1 nK)) over +-log10(1 + 1e8) (clamped).
+ * IAT_REDUCE_BOXCOUNT (a whole square power-of-two GRID batch): box-counting dimensions of the
+ *   complex-forming set.  For boxes of s = 2^k cells, N_set(k) = boxes holding a complex cell and
+ *   N_bnd(k) = boxes holding both kinds; out[0] = D_boundary, out[1] = D_set (least-squares slopes
+ *   of log N against log(1/s) over s = 2..64), out[2+2k] = N_set(k), out[3+2k] = N_bnd(k), k = 0..log2(side);
+ *   side 2..32768; NaN slopes when fewer than two levels have boxes. */
 #define IAT_REDUCE_CELLS 1
 #define IAT_REDUCE_W0_HIST 2
+#define IAT_REDUCE_BOXCOUNT 3
 int iat_reduce(const iat_system* sys, const iat_species* species, int n_species,
                const iat_batch* batch, const iat_obs* obs, int kind, double* out, void* stream);
 
@@ -186,7 +197,12 @@ int iat_reduce(const iat_system* sys, const iat_species* species, int n_species,
  * dobs_dp[15*n] = d(angle, q_transfer, dE_ion)/d(theta, phi, E, q_x, De), laid out
  * [j*15 + 5*i + p]; ftle[n] = ln(sigma_max(Phi(t_f, 0)))/t_f (per a.u. time), Phi the
  * 12x12 stability matrix of the internal state; Phi_out[144*n] (row-major per
- * trajectory, internal units) or NULL.  Head-on GRID/ARRAYS batches only. */
+ * trajectory, internal units) or NULL.  Columns that grow past 2^400 are rescaled as they go
+ * (exponents tracked per column); Phi_out holds Phi * 2^-e with e the largest column exponent,
+ * so e = 0 and Phi_out = Phi unless the stretching passed 2^400 (long-lived complexes), and ftle
+ * accounts for e.  Head-on GRID/ARRAYS batches only; y0 batches are rejected (IAT_ENOTSUP).
+ * Workspace: one device allocation of n*(22*8 + 5*4 + 14*13*8 + 14*4 [+ 144*8 when Phi_out is
+ * NULL and ftle is not]) bytes, stream-ordered on the given stream. */
 int iat_integrate_tangent(const iat_system* sys, const iat_species* species, int n_species,
                           const iat_batch* batch, const iat_obs* obs, double* dobs_dp, double* ftle,
                           double* Phi_out, const iat_launch* launch, void* stream);

@@ -14,7 +14,8 @@ ST_R_UNDERFLOW, ST_WARN_R0, ST_ADJ_SKIPPED = 1 << 12, 1 << 13, 1 << 14
 MAX_SPECIES = 8
 GEN_ARRAYS, GEN_GRID, GEN_SWEEP = 0, 1, 2
 KERNEL_PLAIN, KERNEL_PERSISTENT = 1, 2
-REDUCE_CELLS, REDUCE_W0_HIST = 1, 2
+REDUCE_CELLS, REDUCE_W0_HIST, REDUCE_BOXCOUNT = 1, 2, 3
+W0_BINS, HEAT_BINS = 64, 256
 WS_CKPT, WS_ADJ_SCRATCH = 1, 2
 
 EXPORTS = ["iat_integrate", "iat_integrate_tangent", "iat_adjoint", "iat_reduce", "iat_workspace_bytes",
@@ -58,7 +59,7 @@ class Obs(ctypes.Structure):
 class Launch(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("refill_every", ctypes.c_int32), ("step_budget", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3), ("stats", _vp)]
+                ("reserved", ctypes.c_int32), ("stats", _vp), ("kernel_ms", _vp)]
 
 
 _P = ctypes.POINTER

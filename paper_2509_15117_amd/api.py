@@ -109,22 +109,26 @@ def batch_struct(n: int, gen, arrays: Optional[Dict[str, torch.Tensor]] = None,
 
 
 def launch_struct(kernel="persistent", block=0, blocks_per_cu=0, refill_every=0, step_budget=0,
-                  stats: Optional[torch.Tensor] = None) -> _abi.Launch:
+                  stats: Optional[torch.Tensor] = None, kernel_ms=None) -> _abi.Launch:
+    """kernel_ms: optional host ctypes float[4] for the phase durations (the call then waits)."""
     L = _abi.Launch()
     L.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     L.block, L.blocks_per_cu, L.refill_every = block, blocks_per_cu, refill_every
     L.step_budget = step_budget
     L.stats = _ptr(stats)
+    L.kernel_ms = None if kernel_ms is None else ctypes.cast(kernel_ms, ctypes.c_void_p)
     return L
 
 
 def integrate(system, species, gen, n: int, *, arrays=None, y0=None, id0=None, kernel="persistent", block=0,
               blocks_per_cu=0, refill_every=0, step_budget=0, y_final=False, counters=True, stats=None, out=None,
-              stream=None, device=None) -> Dict[str, torch.Tensor]:
+              stream=None, device=None, kernel_ms=None) -> Dict[str, torch.Tensor]:
     """Integrate n trajectories on the current GPU; returns device tensors of the observables.
 
     system / gen: objects with the fields of workloads.System / workloads.Generator.
-    species: [(m_atom, C4)] in atomic units.  stats: optional uint64[8] device counters (int64 tensor)."""
+    species: [(m_atom, C4)] in atomic units.  stats: optional uint64[8] device counters (int64 tensor).
+    kernel_ms: optional (ctypes.c_float * 4)() receiving the phase durations (setup, main, tail,
+    observables) measured with HIP events on the stream; the call then waits for completion."""
     L = _abi.load()
     device = device or torch.device("cuda", torch.cuda.current_device())
     if out is None:
@@ -133,7 +137,7 @@ def integrate(system, species, gen, n: int, *, arrays=None, y0=None, id0=None, k
     sp = species_array(species)
     b = batch_struct(n, gen, arrays, y0, id0)
     o = obs_struct(out)
-    la = launch_struct(kernel, block, blocks_per_cu, refill_every, step_budget, stats)
+    la = launch_struct(kernel, block, blocks_per_cu, refill_every, step_budget, stats, kernel_ms)
     rc = L.iat_integrate(ctypes.byref(sysv), sp, len(species), ctypes.byref(b), ctypes.byref(o), ctypes.byref(la),
                          None, 0, _stream_handle(stream))
     _abi.check(rc)
@@ -144,3 +148,81 @@ def integrate_workload(w, n=None, id0=None, **kw):
     """Convenience: integrate the first n ids (from id0) of a workloads.Workload."""
     n = w.n if n is None else n
     return integrate(w.system, w.species(), w.gen, n, id0=id0, **kw)
+
+
+def tangent(system, species, gen, n: int, *, arrays=None, id0=None, phi=False, out=None, stream=None,
+            device=None) -> Dict[str, torch.Tensor]:
+    """Observables plus their sensitivities d(angle, q_transfer, dE_ion)/d(theta, phi, E, q_x, De)
+    (key 'dobs_dp', shape n x 3 x 5), the finite-time Lyapunov exponent per a.u. time ('ftle')
+    and, with phi=True, the 12 x 12 stability matrix of the internal state ('Phi')."""
+    L = _abi.load()
+    device = device or torch.device("cuda", torch.cuda.current_device())
+    if out is None:
+        out = alloc_obs(n, device, counters=True)
+    out["dobs_dp"] = torch.empty(n, 3, 5, dtype=torch.float64, device=device)
+    out["ftle"] = torch.empty(n, dtype=torch.float64, device=device)
+    if phi:
+        out["Phi"] = torch.empty(n, 12, 12, dtype=torch.float64, device=device)
+    sysv = system_struct(system)
+    sp = species_array(species)
+    b = batch_struct(n, gen, arrays, None, id0)
+    o = obs_struct(out)
+    la = launch_struct()
+    rc = L.iat_integrate_tangent(ctypes.byref(sysv), sp, len(species), ctypes.byref(b), ctypes.byref(o),
+                                 _ptr(out["dobs_dp"]), _ptr(out["ftle"]), _ptr(out.get("Phi")), ctypes.byref(la),
+                                 _stream_handle(stream))
+    _abi.check(rc)
+    return out
+
+
+def n_cells(gen) -> int:
+    """Number of sweep cells (species x E x q_x x De lists; a range counts as one)."""
+    return max(1, len(gen.species)) * max(1, len(gen.E_list)) * max(1, len(gen.q_list)) * max(1, len(gen.De_list))
+
+
+def _reduce(kind, system, species, gen, n, obs, out, id0, arrays, stream):
+    L = _abi.load()
+    sysv = system_struct(system)
+    sp = species_array(species)
+    b = batch_struct(n, gen, arrays, None, id0)
+    o = obs_struct(obs)
+    rc = L.iat_reduce(ctypes.byref(sysv), sp, len(species), ctypes.byref(b), ctypes.byref(o), kind, _ptr(out),
+                      _stream_handle(stream))
+    _abi.check(rc)
+    return out
+
+
+def reduce_cells(system, species, gen, n, obs, *, id0=None, arrays=None, out=None, stream=None):
+    """Per sweep cell (count, complex count, sum dE_ion, sum dE_ion^2, sum n_bounce), shape n_cells x 5.
+    Passing the previous chunk's out accumulates."""
+    dev = obs["status"].device
+    if out is None:
+        out = torch.zeros(n_cells(gen), 5, dtype=torch.float64, device=dev)
+    return _reduce(_abi.REDUCE_CELLS, system, species, gen, n, obs, out, id0, arrays, stream)
+
+
+def reduce_hist(system, species, gen, n, obs, *, id0=None, arrays=None, out=None, stream=None):
+    """Complex/total counts over log10(E/W0) per species slot (n_slots x 64 x 2) and the heating histogram
+    (256,) in one flat tensor; use split_hist() to view them.  Passing the previous out accumulates."""
+    dev = obs["status"].device
+    slots = len(gen.species) if gen.kind == "sweep" else 1
+    if out is None:
+        out = torch.zeros(slots * 2 * _abi.W0_BINS + _abi.HEAT_BINS, dtype=torch.float64, device=dev)
+    return _reduce(_abi.REDUCE_W0_HIST, system, species, gen, n, obs, out, id0, arrays, stream)
+
+
+def split_hist(flat: torch.Tensor):
+    slots = (flat.numel() - _abi.HEAT_BINS) // (2 * _abi.W0_BINS)
+    return flat[: slots * 2 * _abi.W0_BINS].view(slots, _abi.W0_BINS, 2), flat[slots * 2 * _abi.W0_BINS:]
+
+
+def boxcount(system, species, gen, obs, *, stream=None):
+    """Box-counting dimensions of the complex-forming set of a whole square power-of-two GRID batch:
+    {'D_boundary', 'D_set', 'N_set' (per level k, boxes of 2^k cells), 'N_boundary'}."""
+    side = gen.n_theta
+    levels = side.bit_length()
+    out = torch.zeros(2 + 2 * levels, dtype=torch.float64, device=obs["status"].device)
+    _reduce(_abi.REDUCE_BOXCOUNT, system, species, gen, gen.n_theta * gen.n_phi, obs, out, 0, None, stream)
+    h = out.cpu()
+    return {"D_boundary": float(h[0]), "D_set": float(h[1]), "N_set": h[2::2].long().tolist(),
+            "N_boundary": h[3::2].long().tolist()}

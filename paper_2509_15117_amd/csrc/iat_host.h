@@ -15,5 +15,21 @@ void fill_params(KParams& P, const iat_system* sys, const iat_species* species, 
                  const iat_batch* batch);
 void fill_outputs(KParams& P, const iat_obs* obs);
 int resolve_launch(const iat_launch* launch, iat_launch* out);
+// setup (ids -> start states, lane constants) and observables kernels over a work buffer
+void launch_setup(const KParams& P, const Work& W, hipStream_t st);
+void launch_observe(const KParams& P, const Work& W, hipStream_t st);
+
+// HIP-event timing of a call's phases into a host float[4] (no-op when out is NULL).
+class PhaseTimer {
+public:
+    PhaseTimer(float* out, hipStream_t st);
+    ~PhaseTimer();
+    void mark(int k);      // k = 0..4: before setup, after setup, after main, after tail, after observe
+    int finish();          // waits for the last mark; 0 or an error code
+private:
+    float* out_;
+    hipStream_t st_;
+    hipEvent_t ev_[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+};
 
 }  // namespace iat

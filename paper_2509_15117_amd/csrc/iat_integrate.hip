@@ -167,7 +167,8 @@ __global__ void __launch_bounds__(256) k_integrate_tail(KParams P, Work W, Cont 
     uint64_t iters = 0;
     Traj4 T;
     int64_t i = -1;
-    int32_t resumed_at = 0;
+    int32_t resumed_at = 0, resumed_rhs = 0;
+    uint64_t tail_rhs = 0, tail_done = 0;
     bool active = false, need = true;
     for (;;) {
         const uint64_t mask = __ballot(need && leader);
@@ -182,6 +183,7 @@ __global__ void __launch_bounds__(256) k_integrate_tail(KParams P, Work W, Cont 
                 if (active) {
                     cont_load4(P, W, C, slot, k, T, i);
                     resumed_at = T.S.nacc + T.S.nrej;
+                    resumed_rhs = T.S.nrhs;
                 }
                 need = false;
             }
@@ -197,6 +199,8 @@ __global__ void __launch_bounds__(256) k_integrate_tail(KParams P, Work W, Cont 
                 st.rej += T.S.nrej;
                 st.done += 1;
                 st.useful += T.S.nacc + T.S.nrej - resumed_at;
+                tail_rhs += (uint64_t)(T.S.nrhs - resumed_rhs);
+                tail_done += 1;
             }
             active = false;
             need = true;
@@ -204,7 +208,14 @@ __global__ void __launch_bounds__(256) k_integrate_tail(KParams P, Work W, Cont 
     }
     // a wave carries 16 trajectories: 16 step slots per iteration
     flush_stats(P.stats, st, 0ull);
-    if (P.stats && lane == 0) atomicAdd((unsigned long long*)&P.stats[4], (unsigned long long)(16ull * iters));
+    if (P.stats) {
+        const uint64_t tr = wave_sum(tail_rhs), td = wave_sum(tail_done);
+        if (lane == 0) {
+            atomicAdd((unsigned long long*)&P.stats[4], (unsigned long long)(16ull * iters));
+            atomicAdd((unsigned long long*)&P.stats[6], (unsigned long long)tr);
+            atomicAdd((unsigned long long*)&P.stats[7], (unsigned long long)td);
+        }
+    }
 }
 
 __global__ void k_reset_counters(unsigned long long* q, int n)
@@ -381,6 +392,34 @@ void fill_outputs(KParams& P, const iat_obs* obs)
     P.y_final = obs->y_final;
 }
 
+// Optional phase timing with HIP events on the call's stream (launch.kernel_ms).
+PhaseTimer::PhaseTimer(float* out, hipStream_t st) : out_(out), st_(st)
+{
+    if (!out_) return;
+    for (int k = 0; k < 5; ++k)
+        if (hipEventCreate(&ev_[k]) != hipSuccess) ev_[k] = nullptr;
+}
+void PhaseTimer::mark(int k)
+{
+    if (out_ && ev_[k]) hipEventRecord(ev_[k], st_);
+}
+int PhaseTimer::finish()
+{
+    if (!out_) return 0;
+    int rc = 0;
+    if (hipEventSynchronize(ev_[4]) != hipSuccess) rc = set_error(IAT_EHIP, "timing: hipEventSynchronize failed");
+    for (int k = 0; k < 4 && rc == 0; ++k)
+        if (hipEventElapsedTime(&out_[k], ev_[k], ev_[k + 1]) != hipSuccess)
+            rc = set_error(IAT_EHIP, "timing: hipEventElapsedTime failed");
+    return rc;
+}
+PhaseTimer::~PhaseTimer()
+{
+    if (!out_) return;
+    for (int k = 0; k < 5; ++k)
+        if (ev_[k]) hipEventDestroy(ev_[k]);
+}
+
 int resolve_launch(const iat_launch* launch, iat_launch* out)
 {
     iat_launch L{};
@@ -403,6 +442,17 @@ int resolve_launch(const iat_launch* launch, iat_launch* out)
 }  // namespace iat
 
 using namespace iat;
+
+namespace iat {
+void launch_setup(const KParams& P, const Work& W, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_setup, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, P, W);
+}
+void launch_observe(const KParams& P, const Work& W, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_observe, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, P, W);
+}
+}  // namespace iat
 
 extern "C" int iat_integrate(const iat_system* sys, const iat_species* species, int n_species,
                              const iat_batch* batch, const iat_obs* obs, const iat_launch* launch,
@@ -456,8 +506,11 @@ extern "C" int iat_integrate(const iat_system* sys, const iat_species* species, 
     C.d = (double*)((char*)ws + 256 + ((work_bytes + 255) / 256) * 256);
     C.n = (int32_t*)(C.d + 26 * cap);
     C.id = (int64_t*)(C.n + 8 * cap);
+    PhaseTimer timer(L.kernel_ms, st);
     hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, st, q, 4);
+    timer.mark(0);
     hipLaunchKernelGGL(k_setup, dim3(nblk), dim3(256), 0, st, P, W);
+    timer.mark(1);
     if (L.kernel == IAT_KERNEL_PLAIN) {
         hipLaunchKernelGGL(k_integrate_plain, dim3((unsigned)((n + L.block - 1) / L.block)), dim3(L.block), 0, st, P, W);
     } else {
@@ -471,6 +524,7 @@ extern "C" int iat_integrate(const iat_system* sys, const iat_species* species, 
         const int64_t need = (n + L.block - 1) / L.block;
         if (blocks > need) blocks = need;
         hipLaunchKernelGGL(k_integrate_persistent, dim3((unsigned)blocks), dim3(L.block), 0, st, P, W, q, C);
+        timer.mark(2);
         if (cap > 0) {
             int per_cu4 = 1;
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu4, (const void*)k_integrate_tail, 256, 0) !=
@@ -482,11 +536,14 @@ extern "C" int iat_integrate(const iat_system* sys, const iat_species* species, 
             hipLaunchKernelGGL(k_integrate_tail, dim3((unsigned)blocks4), dim3(256), 0, st, P, W, C);
         }
     }
+    if (L.kernel == IAT_KERNEL_PLAIN) timer.mark(2);
+    timer.mark(3);
     hipLaunchKernelGGL(k_observe, dim3(nblk), dim3(256), 0, st, P, W);
+    timer.mark(4);
     if (hipFreeAsync(ws, st) != hipSuccess) return set_error(IAT_EHIP, "hipFreeAsync failed");
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(IAT_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
-    return 0;
+    return timer.finish();
 }
 
 extern "C" const char* iat_last_error(void) { return iat::last_error(); }

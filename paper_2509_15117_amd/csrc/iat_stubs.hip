@@ -3,11 +3,6 @@
 
 using namespace iat;
 
-extern "C" int iat_integrate_tangent(const iat_system*, const iat_species*, int, const iat_batch*,
-                                     const iat_obs*, double*, double*, double*, const iat_launch*, void*)
-{
-    return set_error(IAT_ENOTSUP, "iat_integrate_tangent is not implemented yet");
-}
 
 extern "C" int iat_adjoint(const iat_system*, const iat_species*, int, const iat_batch*, const iat_obs*,
                            const double*, double*, const void*, size_t, void*, size_t, const iat_launch*, void*)
@@ -15,11 +10,6 @@ extern "C" int iat_adjoint(const iat_system*, const iat_species*, int, const iat
     return set_error(IAT_ENOTSUP, "iat_adjoint is not implemented yet");
 }
 
-extern "C" int iat_reduce(const iat_system*, const iat_species*, int, const iat_batch*, const iat_obs*, int,
-                          double*, void*)
-{
-    return set_error(IAT_ENOTSUP, "iat_reduce is not implemented yet");
-}
 
 extern "C" int iat_workspace_bytes(int, const iat_system*, const iat_batch*, size_t*)
 {
