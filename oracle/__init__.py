@@ -273,14 +273,21 @@ def philox4x64_10(ctr, key):
     return o
 
 
-def tangent(problem, theta, phi, E, q_ratio):
-    """d(angle, q, dE)/d(theta, phi, E, q_x, De), Phi(t_f, 0) and the FTLE (internal time)."""
+def tangent(problem, theta, phi, E, q_ratio, twin: bool = False):
+    """d(angle, q, dE)/d(theta, phi, E, q_x, De), Phi(t_f, 0) and the FTLE (internal time).
+    twin=True runs the round-off twin build."""
     p = np.ascontiguousarray(np.asarray(problem, dtype=PROBLEM).reshape(1))
     qr = np.ascontiguousarray(q_ratio, dtype=np.float64)
     d = np.zeros(15)
     Phi = np.zeros(144)
     ftle = ctypes.c_double()
-    rc = lib().orc_tangent(_ptr(p), theta, phi, E, _dptr(qr), _dptr(d), _dptr(Phi), ctypes.byref(ftle))
+    L = lib()
+    if twin:
+        T = twin_lib()
+        T.orc_tangent.argtypes = L.orc_tangent.argtypes
+        T.orc_tangent.restype = L.orc_tangent.restype
+        L = T
+    rc = L.orc_tangent(_ptr(p), theta, phi, E, _dptr(qr), _dptr(d), _dptr(Phi), ctypes.byref(ftle))
     if rc != 0:
         raise RuntimeError(f"orc_tangent failed ({rc})")
     return d.reshape(3, 5), Phi.reshape(12, 12), ftle.value

@@ -184,7 +184,8 @@ __global__ void k_boxcount_fit(const unsigned long long* counts, int levels, int
             sxy += x * y;
             ++m;
         }
-        out[w] = m >= 2 ? (m * sxy - sx * sy) / (m * sxx - sx * sx) : __builtin_nan("");
+        // w = 0 counts occupied boxes (D_set, out[1]); w = 1 boundary boxes (D_boundary, out[0])
+        out[1 - w] = m >= 2 ? (m * sxy - sx * sy) / (m * sxx - sx * sx) : __builtin_nan("");
     }
     for (int k = 0; k < levels; ++k) {
         out[2 + 2 * k] = (double)counts[2 * k];

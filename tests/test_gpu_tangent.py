@@ -20,7 +20,31 @@ def _scales(w):
     return np.array([1.0, 1.0, w.system.E, w.system.q_x, w.system.De])
 
 
+def tangent_spread(p, th, ph, w):
+    """Round-off spread of the oracle's tangent for one trajectory: the worst difference, per
+    observable (norm of the parameter-scaled gradient) and for Phi (max entry), between the oracle
+    and five round-off probes of it (the FMA twin build and +-1 ulp start positions).  The tangent
+    is far worse conditioned than the final state: a collision that stretches phase space by 10^3
+    turns a round-off shift of the trajectory into a relative change of Phi near 1e-6."""
+    s = _scales(w)
+    d, Phi, _ = oracle.tangent(p, th, ph, w.system.E, w.system.q_ratio)
+    runs = [oracle.tangent(p, th, ph, w.system.E, w.system.q_ratio, twin=True)]
+    for sg in PT.PROBE_SIGNS:
+        q = p.copy()
+        q["y0"][0:3] *= 1.0 + sg * 2.0 ** -52
+        runs.append(oracle.tangent(q, th, ph, w.system.E, w.system.q_ratio))
+    sd = np.zeros(3)
+    sp = 0.0
+    for d2, P2, _ in runs:
+        for k in range(3):
+            sd[k] = max(sd[k], np.linalg.norm((d2[k] - d[k]) * s))
+        sp = max(sp, np.abs(P2 - Phi).max())
+    return d, Phi, sd, sp
+
+
 def test_tangent_matches_oracle_tangent_on_direct_trajectories():
+    """Per direct trajectory: each observable's scaled gradient within max(1e-9 |g|, 10 x spread) of the
+    oracle's, and Phi within max(1e-9 max|Phi|, 10 x spread) entrywise."""
     w = W.config1()
     out = PT.to_numpy(api.tangent(w.system, w.species(), w.gen, 64, phi=True))
     P = oracle.problems_for(w, range(64))
@@ -29,14 +53,20 @@ def test_tangent_matches_oracle_tangent_on_direct_trajectories():
     s = _scales(w)
     for gid in DIRECT:
         assert ref[gid]["n_bounce"] == 1 and out["n_bounce"][gid] == 1
-        d, Phi, _ = oracle.tangent(P[gid], th_ph[gid][0], th_ph[gid][1], w.system.E, w.system.q_ratio)
+        d, Phi, sd, sp = tangent_spread(P[gid], th_ph[gid][0], th_ph[gid][1], w)
         g = out["dobs_dp"][gid]
         for k in range(3):
             a, b = g[k] * s, d[k] * s
-            assert np.linalg.norm(a - b) <= 1e-6 * np.linalg.norm(b), (gid, k, a, b)
+            err = np.linalg.norm(a - b)
+            bar = max(1e-9 * np.linalg.norm(b), 10.0 * sd[k])
+            print(f"gid {gid} obs {k}: |dg|/|g| = {err / np.linalg.norm(b):.2e}, "
+                  f"spread {sd[k] / np.linalg.norm(b):.2e}", flush=True)
+            assert err <= bar, (gid, k, a, b, sd[k])
+            assert bar <= 5e-4 * np.linalg.norm(b)      # the bar itself stays meaningful
         Pg = out["Phi"][gid]
-        assert np.abs(Pg - Phi).max() <= 1e-6 * np.abs(Phi).max(), gid
-        # the observables of the tangent run are those of iat_integrate
+        err = np.abs(Pg - Phi).max()
+        assert err <= max(1e-9 * np.abs(Phi).max(), 10.0 * sp), (gid, err, sp)
+    # the observables of the tangent run are those of iat_integrate
     plain = PT.to_numpy(api.integrate_workload(w, kernel="plain", y_final=True))
     for k in ("angle", "q_transfer", "dE_ion", "t_dwell", "n_bounce", "status"):
         assert np.array_equal(out[k], plain[k]), k
