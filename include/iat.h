@@ -166,8 +166,8 @@ typedef struct {
 } iat_launch;
 
 /* Integrate a batch (the paper's head-on runs: model paragraph, head-on-run paragraph,
- * observables of the Fig. 1 caption).  ckpt_ws/ckpt_bytes: adjoint checkpoint workspace
- * (see iat_adjoint), or NULL/0.  Returns 0 or an error code. */
+ * observables of the Fig. 1 caption).  ckpt_ws/ckpt_bytes: reserved, pass NULL/0 (iat_adjoint
+ * stores its own checkpoints).  Returns 0 or an error code. */
 int iat_integrate(const iat_system* sys, const iat_species* species /* host */, int n_species,
                   const iat_batch* batch, const iat_obs* obs, const iat_launch* launch,
                   void* ckpt_ws, size_t ckpt_bytes, void* stream);
@@ -207,19 +207,29 @@ int iat_integrate_tangent(const iat_system* sys, const iat_species* species, int
                           const iat_batch* batch, const iat_obs* obs, double* dobs_dp, double* ftle,
                           double* Phi_out, const iat_launch* launch, void* stream);
 
-/* Discrete adjoint of the accepted-step map: p_bar[5*n] = (d/dp) sum_k obs_bar[3*j+k] obs_k
- * for p = (theta, phi, E, q_x, De), using checkpoints (state, time, step) that iat_integrate
- * stored every 256 accepted steps in ckpt_ws; segments are recomputed in scratch.
- * Trajectories that did not fit the workspace get NaN and IAT_ST_ADJ_SKIPPED. */
+/* Discrete adjoint of the accepted-step map (the sensitivities of the scattering observables of
+ * the Fig. 1 caption to the start and model parameters).  Per trajectory j:
+ *   p_bar[5*j + p] = d/dp sum_k obs_bar[3*j + k] obs_k,   obs = (angle, q_transfer, dE_ion),
+ *   p = (theta, phi, E, q_x, De),
+ * the exact derivative of the same discrete map that iat_integrate_tangent differentiates
+ * (accepted steps with their sizes frozen, the exit time moved by the event |r_a - r_i| = r0).
+ * obs must hold the iat_integrate outputs of this same batch: n_accept (device int64[n]) sizes
+ * the checkpoints (one every 256 accepted steps, 192 bytes each), status selects the
+ * trajectories (exited or t_max); the call sets IAT_ST_ADJ_SKIPPED in obs.status and writes NaN
+ * to p_bar for the others, and for any trajectory whose checkpoints do not fit ws.
+ * obs_bar: device double[3*n]; p_bar: device double[5*n].
+ * ws/ws_bytes: device workspace of at least iat_adjoint_workspace_bytes() bytes; ws = NULL makes
+ * the call size (one stream synchronisation) and allocate it itself, stream-ordered.
+ * Head-on GRID/SWEEP/ARRAYS batches only (y0 batches: IAT_ENOTSUP).  Gradients that pass the
+ * double range come out as +-inf. */
 int iat_adjoint(const iat_system* sys, const iat_species* species, int n_species,
                 const iat_batch* batch, const iat_obs* obs, const double* obs_bar, double* p_bar,
-                const void* ckpt_ws, size_t ckpt_bytes, void* scratch, size_t scratch_bytes,
-                const iat_launch* launch, void* stream);
+                void* ws, size_t ws_bytes, const iat_launch* launch, void* stream);
 
-#define IAT_WS_CKPT 1
-#define IAT_WS_ADJ_SCRATCH 2
-/* Bytes needed for a workspace (host query). */
-int iat_workspace_bytes(int which, const iat_system* sys, const iat_batch* batch, size_t* bytes);
+/* Device workspace bytes iat_adjoint needs for this batch (reads obs.n_accept and obs.status of
+ * its iat_integrate run on the stream and synchronises it). */
+int iat_adjoint_workspace_bytes(const iat_system* sys, const iat_species* species, int n_species,
+                                const iat_batch* batch, const iat_obs* obs, size_t* bytes, void* stream);
 
 const char* iat_last_error(void);
 /* Library version string. */

@@ -16,9 +16,8 @@ GEN_ARRAYS, GEN_GRID, GEN_SWEEP = 0, 1, 2
 KERNEL_PLAIN, KERNEL_PERSISTENT = 1, 2
 REDUCE_CELLS, REDUCE_W0_HIST, REDUCE_BOXCOUNT = 1, 2, 3
 W0_BINS, HEAT_BINS = 64, 256
-WS_CKPT, WS_ADJ_SCRATCH = 1, 2
 
-EXPORTS = ["iat_integrate", "iat_integrate_tangent", "iat_adjoint", "iat_reduce", "iat_workspace_bytes",
+EXPORTS = ["iat_integrate", "iat_integrate_tangent", "iat_adjoint", "iat_reduce", "iat_adjoint_workspace_bytes",
            "iat_last_error", "iat_version", "iat_release"]
 
 _d = ctypes.c_double
@@ -88,10 +87,11 @@ def load():
                                         _vp, _P(Launch), _vp]
     L.iat_integrate_tangent.restype = ctypes.c_int
     L.iat_adjoint.argtypes = [_P(System), _P(Species), ctypes.c_int, _P(Batch), _P(Obs), _vp, _vp, _vp,
-                              ctypes.c_size_t, _vp, ctypes.c_size_t, _P(Launch), _vp]
+                              ctypes.c_size_t, _P(Launch), _vp]
     L.iat_adjoint.restype = ctypes.c_int
-    L.iat_workspace_bytes.argtypes = [ctypes.c_int, _P(System), _P(Batch), _P(ctypes.c_size_t)]
-    L.iat_workspace_bytes.restype = ctypes.c_int
+    L.iat_adjoint_workspace_bytes.argtypes = [_P(System), _P(Species), ctypes.c_int, _P(Batch), _P(Obs),
+                                              _P(ctypes.c_size_t), _vp]
+    L.iat_adjoint_workspace_bytes.restype = ctypes.c_int
     L.iat_last_error.restype = ctypes.c_char_p
     L.iat_version.restype = ctypes.c_char_p
     L.iat_release.restype = None

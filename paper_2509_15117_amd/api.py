@@ -226,3 +226,69 @@ def boxcount(system, species, gen, obs, *, stream=None):
     h = out.cpu()
     return {"D_boundary": float(h[0]), "D_set": float(h[1]), "N_set": h[2::2].long().tolist(),
             "N_boundary": h[3::2].long().tolist()}
+
+
+def adjoint(system, species, gen, n: int, obs: Dict[str, torch.Tensor], obs_bar: torch.Tensor, *, arrays=None,
+            id0=None, ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """p_bar (n x 5) = d/d(theta, phi, E, q_x, De) of sum_k obs_bar[:, k] obs_k, obs = (angle, q_transfer,
+    dE_ion), by the discrete adjoint.  obs: the outputs of integrate() on the same batch with counters
+    (n_accept); obs['status'] gains ADJ_SKIPPED where the gradient is NaN.  ws: optional uint8 device
+    workspace of adjoint_workspace_bytes() bytes (else allocated by the library)."""
+    L = _abi.load()
+    obs_bar = obs_bar.contiguous()
+    if obs_bar.shape != (n, 3) or obs_bar.dtype != torch.float64:
+        raise ValueError("obs_bar must be a float64 tensor of shape (n, 3)")
+    if "n_accept" not in obs:
+        raise ValueError("obs must come from integrate(..., counters=True) of the same batch")
+    p_bar = torch.empty(n, 5, dtype=torch.float64, device=obs_bar.device)
+    sysv = system_struct(system)
+    sp = species_array(species)
+    b = batch_struct(n, gen, arrays, None, id0)
+    o = obs_struct(obs)
+    la = launch_struct()
+    rc = L.iat_adjoint(ctypes.byref(sysv), sp, len(species), ctypes.byref(b), ctypes.byref(o), _ptr(obs_bar),
+                       _ptr(p_bar), _ptr(ws), 0 if ws is None else ws.numel() * ws.element_size(),
+                       ctypes.byref(la), _stream_handle(stream))
+    _abi.check(rc)
+    return p_bar
+
+
+def adjoint_workspace_bytes(system, species, gen, n: int, obs, *, arrays=None, id0=None, stream=None) -> int:
+    L = _abi.load()
+    sysv = system_struct(system)
+    sp = species_array(species)
+    b = batch_struct(n, gen, arrays, None, id0)
+    o = obs_struct(obs)
+    out = ctypes.c_size_t(0)
+    rc = L.iat_adjoint_workspace_bytes(ctypes.byref(sysv), sp, len(species), ctypes.byref(b), ctypes.byref(o),
+                                       ctypes.byref(out), _stream_handle(stream))
+    _abi.check(rc)
+    return int(out.value)
+
+
+class ScatteringObservables(torch.autograd.Function):
+    """obs = (angle, q_transfer, dE_ion) per trajectory as a differentiable function of per-trajectory
+    (theta, phi, E, q_x, De) tensors (float64, device, length n); the backward pass is the library's
+    discrete adjoint.  Usage: ScatteringObservables.apply(theta, phi, E, q_x, De, system, species, gen)
+    with gen.kind == 'arrays' (species / phase0 from the system, or gen-level arrays via `extra`)."""
+
+    @staticmethod
+    def forward(ctx, theta, phi, E, q_x, De, system, species, gen, extra=None):
+        arrays = {"theta": theta.contiguous(), "phi": phi.contiguous(), "E": E.contiguous(),
+                  "q_x": q_x.contiguous(), "De": De.contiguous()}
+        if extra:
+            arrays.update({k: v.contiguous() for k, v in extra.items()})
+        n = theta.numel()
+        out = integrate(system, species, gen, n, arrays=arrays, counters=True)
+        ctx.save_for_backward(*arrays.values())
+        ctx.keys = list(arrays.keys())
+        ctx.cfg = (system, species, gen, n)
+        ctx.obs = out
+        return torch.stack([out["angle"], out["q_transfer"], out["dE_ion"]], dim=1)
+
+    @staticmethod
+    def backward(ctx, grad):
+        system, species, gen, n = ctx.cfg
+        arrays = dict(zip(ctx.keys, ctx.saved_tensors))
+        p_bar = adjoint(system, species, gen, n, ctx.obs, grad.to(torch.float64).contiguous(), arrays=arrays)
+        return p_bar[:, 0], p_bar[:, 1], p_bar[:, 2], p_bar[:, 3], p_bar[:, 4], None, None, None, None

@@ -824,11 +824,44 @@ __device__ __forceinline__ void accel4(const KParams& P, const Lane& L, int k, d
     Ai = acc_ion(P.inv_mi, s, dk, kA, qc, qr, Xi);
 }
 
-__device__ __forceinline__ void traj4_advance(const KParams& P, Traj4& T)
+// Start of a four-lane trajectory from the work buffer (same bits as traj1_start).
+__device__ inline void traj4_start(const KParams& P, const Work& W, int64_t i, Traj4& T)
+{
+    const int k = quad_axis();
+    work_lane(W, i, T.L);
+    scal_init(P, T.S);
+    T.S.status = (uint32_t)W.k(4, i);
+    T.xa = W.d(k, i);
+    T.xi = W.d(3 + k, i);
+    T.va = W.d(6 + k, i);
+    T.vi = W.d(9 + k, i);
+    T.F1a = T.F1i = 0.0;
+    const int nonfin = quad_or((is_finite(T.xa) && is_finite(T.xi) && is_finite(T.va) && is_finite(T.vi)) ? 0 : 1);
+    if (nonfin) {
+        T.S.status |= IAT_ST_NONFINITE;
+        T.S.done = 1;
+        return;
+    }
+    double s0, c0;
+    phase_sincos(T.L.phase0, s0, c0);
+    accel4(P, T.L, k, c0, T.xa, T.xi, T.F1a, T.F1i);
+    T.S.nrhs = 1;
+    const double dk = T.xa - T.xi, wk = T.va - T.vi;
+    const double d0 = quad_bcast<0>(dk), d1 = quad_bcast<1>(dk), d2 = quad_bcast<2>(dk);
+    const double w0 = quad_bcast<0>(wk), w1 = quad_bcast<1>(wk), w2 = quad_bcast<2>(wk);
+    T.S.rho_prev = dot3(d0, d1, d2, d0, d1, d2);
+    T.S.s_prev = dot3(d0, d1, d2, w0, w1, w2);
+}
+
+// One attempted step of the four-lane form.  Returns the StepOutcome, or -1 when the trajectory
+// stopped before stepping (step cap, step underflow); h_used receives the step size tried.
+__device__ __forceinline__ int traj4_step(const KParams& P, Traj4& T, double& h_used)
 {
     double h;
     bool fin;
-    if (!step_prologue(P, T.S, h, fin)) return;
+    h_used = 0.0;
+    if (!step_prologue(P, T.S, h, fin)) return -1;
+    h_used = h;
     const bool exiting = T.S.mode != 0;
     const int k = quad_axis();
     const double hh = h * h;
@@ -881,6 +914,13 @@ __device__ __forceinline__ void traj4_advance(const KParams& P, Traj4& T)
         T.F1a = F7a;
         T.F1i = F7i;
     }
+    return (int)o;
+}
+
+__device__ __forceinline__ void traj4_advance(const KParams& P, Traj4& T)
+{
+    double h;
+    (void)traj4_step(P, T, h);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -401,7 +401,7 @@ PhaseTimer::PhaseTimer(float* out, hipStream_t st) : out_(out), st_(st)
 }
 void PhaseTimer::mark(int k)
 {
-    if (out_ && ev_[k]) hipEventRecord(ev_[k], st_);
+    if (out_ && ev_[k]) (void)hipEventRecord(ev_[k], st_);
 }
 int PhaseTimer::finish()
 {
@@ -417,7 +417,7 @@ PhaseTimer::~PhaseTimer()
 {
     if (!out_) return;
     for (int k = 0; k < 5; ++k)
-        if (ev_[k]) hipEventDestroy(ev_[k]);
+        if (ev_[k]) (void)hipEventDestroy(ev_[k]);
 }
 
 int resolve_launch(const iat_launch* launch, iat_launch* out)

@@ -1,0 +1,146 @@
+"""GPU discrete adjoint (iat_adjoint) against the GPU tangent-linear, the oracle's tangent and
+central differences of the oracle.
+
+* Adjoint and tangent differentiate the same discrete map along the same primal bits, so
+  obs_bar . dobs/dp from the tangent equals the adjoint's p_bar up to the rounding of the two
+  association orders of the Jacobian products: 1e-9 relative on direct trajectories.
+* Against the oracle's tangent the bar is the oracle's own round-off spread (as for the tangent).
+* Central differences of the oracle's frozen-step map resolve these sensitivities only to a few
+  1e-5 in FP64 at their best step (truncation O(h^2) of a strongly curved map above, round-off
+  amplified by the collision below): the adjoint must agree to 2e-4 at the best of the steps.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests import _parity as PT
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2509_15117_amd import api  # noqa: E402
+from paper_2509_15117_amd import _abi  # noqa: E402
+
+DIRECT = [40, 41, 47, 51, 55, 58, 63]
+DEV = torch.device("cuda", 0)
+
+
+def _scales(w):
+    return np.array([1.0, 1.0, w.system.E, w.system.q_x, w.system.De])
+
+
+def _run(w, n, seed=0):
+    obs = api.integrate_workload(w, n=n, counters=True)
+    g = torch.from_numpy(np.random.default_rng(seed).normal(size=(n, 3))).to(DEV)
+    print(f"adjoint: {w.name}, n={n}", flush=True)
+    pb = api.adjoint(w.system, w.species(), w.gen, n, obs, g)
+    torch.cuda.synchronize()
+    return obs, g.cpu().numpy(), pb.cpu().numpy()
+
+
+def test_adjoint_equals_tangent_contraction():
+    w = W.config1()
+    obs, g, pb = _run(w, 64)
+    tan = PT.to_numpy(api.tangent(w.system, w.species(), w.gen, 64))
+    ref = np.einsum("ik,ikp->ip", g, tan["dobs_dp"])
+    s = _scales(w)
+    st = obs["status"].cpu().numpy()
+    nb = obs["n_bounce"].cpu().numpy()
+    worst_direct, worst_all = 0.0, 0.0
+    for i in range(64):
+        assert (st[i] & _abi.ST_ADJ_SKIPPED) == 0, i
+        a, b = pb[i] * s, ref[i] * s
+        if not (np.all(np.isfinite(a)) and np.all(np.isfinite(b))):
+            continue
+        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+        worst_all = max(worst_all, rel)
+        if nb[i] <= 1:
+            worst_direct = max(worst_direct, rel)
+            assert rel <= 1e-9, (i, a, b)
+    print(f"adjoint vs tangent: direct {worst_direct:.2e}, all finite {worst_all:.2e}", flush=True)
+    assert worst_all <= 1e-6
+
+
+def test_adjoint_against_oracle_tangent_and_differences():
+    w = W.config1()
+    obs, g, pb = _run(w, 64, seed=1)
+    P = oracle.problems_for(w, range(64))
+    thph = oracle.grid_angles(range(64), 8, 8)
+    s = _scales(w)
+    for gid in DIRECT:
+        d, _, _ = oracle.tangent(P[gid], *thph[gid], w.system.E, w.system.q_ratio)
+        b = (g[gid][:, None] * d).sum(0) * s
+        # round-off spread of the oracle's contraction over its probes
+        spread = 0.0
+        runs = [oracle.tangent(P[gid], *thph[gid], w.system.E, w.system.q_ratio, twin=True)]
+        for sg in PT.PROBE_SIGNS:
+            q = P[gid].copy()
+            q["y0"][0:3] *= 1.0 + sg * 2.0 ** -52
+            runs.append(oracle.tangent(q, *thph[gid], w.system.E, w.system.q_ratio))
+        for d2, _, _ in runs:
+            spread = max(spread, np.linalg.norm((g[gid][:, None] * d2).sum(0) * s - b))
+        a = pb[gid] * s
+        err = np.linalg.norm(a - b)
+        print(f"gid {gid}: |adj - oracle tangent|/|g| = {err / np.linalg.norm(b):.2e} "
+              f"(spread {spread / np.linalg.norm(b):.2e})", flush=True)
+        assert err <= max(1e-9 * np.linalg.norm(b), 10.0 * spread)
+        best = min(np.linalg.norm((g[gid][:, None] * oracle.fd(P[gid], *thph[gid], w.system.E, w.system.q_ratio, h))
+                                  .sum(0) * s - a) for h in (1e-6, 3e-7, 1e-7))
+        print(f"gid {gid}: |adj - FD|/|g| at the best step = {best / np.linalg.norm(a):.2e}", flush=True)
+        assert best <= 2e-4 * np.linalg.norm(a)
+
+
+def test_adjoint_workspace_and_skipping():
+    """A workspace that holds the fixed part and only some records: the trajectories that fit get the
+    same bits as with a full workspace, the others NaN and the skipped status bit."""
+    w = W.config1()
+    obs, g, full = _run(w, 64, seed=2)
+    need = api.adjoint_workspace_bytes(w.system, w.species(), w.gen, 64, obs)
+    assert need > 0
+    ws = torch.empty(need, dtype=torch.uint8, device=DEV)
+    gt = torch.from_numpy(g).to(DEV)
+    again = api.adjoint(w.system, w.species(), w.gen, 64, obs, gt, ws=ws).cpu().numpy()
+    assert np.array_equal(np.isnan(again), np.isnan(full)) and np.array_equal(again[~np.isnan(full)],
+                                                                                full[~np.isnan(full)])
+    nacc = obs["n_accept"].cpu().numpy()
+    recs = nacc // 256 + 2
+    small = need - int(recs.sum() // 2) * 192
+    obs2 = api.integrate_workload(w, n=64, counters=True)
+    part = api.adjoint(w.system, w.species(), w.gen, 64, obs2, gt,
+                       ws=torch.empty(small, dtype=torch.uint8, device=DEV)).cpu().numpy()
+    st = obs2["status"].cpu().numpy()
+    skipped = (st & _abi.ST_ADJ_SKIPPED) != 0
+    assert skipped.any() and (~skipped).any()
+    assert np.all(np.isnan(part[skipped]))
+    assert np.array_equal(part[~skipped], full[~skipped])
+
+
+def test_autograd_function_matches_adjoint():
+    w = W.config1()
+    n = 16
+    ids = np.arange(40, 40 + n)
+    thph = oracle.grid_angles(ids, 8, 8)
+    theta = torch.tensor(thph[:, 0], dtype=torch.float64, device=DEV, requires_grad=True)
+    phi = torch.tensor(thph[:, 1], dtype=torch.float64, device=DEV, requires_grad=True)
+    E = torch.full((n,), w.system.E, dtype=torch.float64, device=DEV, requires_grad=True)
+    q = torch.full((n,), w.system.q_x, dtype=torch.float64, device=DEV, requires_grad=True)
+    De = torch.full((n,), w.system.De, dtype=torch.float64, device=DEV, requires_grad=True)
+    gen = W.Generator(kind="arrays")
+    obs = api.ScatteringObservables.apply(theta, phi, E, q, De, w.system, w.species(), gen)
+    gbar = torch.from_numpy(np.random.default_rng(3).normal(size=(n, 3))).to(DEV)
+    (obs * gbar).sum().backward()
+    # the same observables as the grid batch of these ids, and the gradient of the tangent
+    grid = api.integrate_workload(w, n=64, counters=True)
+    for k, name in enumerate(("angle", "q_transfer", "dE_ion")):
+        assert torch.equal(obs[:, k].detach(), grid[name][40:40 + n]), name
+    tan = PT.to_numpy(api.tangent(w.system, w.species(), w.gen, 64))["dobs_dp"][40:40 + n]
+    ref = np.einsum("ik,ikp->ip", gbar.cpu().numpy(), tan)
+    got = np.stack([t.grad.cpu().numpy() for t in (theta, phi, E, q, De)], axis=1)
+    s = _scales(w)
+    nb = grid["n_bounce"][40:40 + n].cpu().numpy()
+    for i in range(n):
+        if nb[i] <= 1:
+            assert np.linalg.norm((got[i] - ref[i]) * s) <= 1e-9 * np.linalg.norm(ref[i] * s), i
