@@ -217,14 +217,16 @@ int iat_integrate_tangent(const iat_system* sys, const iat_species* species, int
  * the checkpoints (one every 256 accepted steps, 192 bytes each), status selects the
  * trajectories (exited or t_max); the call sets IAT_ST_ADJ_SKIPPED in obs.status and writes NaN
  * to p_bar for the others, and for any trajectory whose checkpoints do not fit ws.
- * obs_bar: device double[3*n]; p_bar: device double[5*n].
+ * obs_bar: device double[3*n]; p_bar: device double[5*n]; y0_bar: device double[12*n] or NULL,
+ * receiving dJ/dy0 for the start state in a.u. (atom and ion positions in a0, velocities in a.u.;
+ * the explicit dependence of the angle and q on the start velocity included).
  * ws/ws_bytes: device workspace of at least iat_adjoint_workspace_bytes() bytes; ws = NULL makes
  * the call size (one stream synchronisation) and allocate it itself, stream-ordered.
  * Head-on GRID/SWEEP/ARRAYS batches only (y0 batches: IAT_ENOTSUP).  Gradients that pass the
  * double range come out as +-inf. */
 int iat_adjoint(const iat_system* sys, const iat_species* species, int n_species,
                 const iat_batch* batch, const iat_obs* obs, const double* obs_bar, double* p_bar,
-                void* ws, size_t ws_bytes, const iat_launch* launch, void* stream);
+                double* y0_bar, void* ws, size_t ws_bytes, const iat_launch* launch, void* stream);
 
 /* Device workspace bytes iat_adjoint needs for this batch (reads obs.n_accept and obs.status of
  * its iat_integrate run on the stream and synchronises it). */

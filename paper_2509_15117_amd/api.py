@@ -229,11 +229,12 @@ def boxcount(system, species, gen, obs, *, stream=None):
 
 
 def adjoint(system, species, gen, n: int, obs: Dict[str, torch.Tensor], obs_bar: torch.Tensor, *, arrays=None,
-            id0=None, ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+            id0=None, ws: Optional[torch.Tensor] = None, y0_bar: bool = False, stream=None):
     """p_bar (n x 5) = d/d(theta, phi, E, q_x, De) of sum_k obs_bar[:, k] obs_k, obs = (angle, q_transfer,
     dE_ion), by the discrete adjoint.  obs: the outputs of integrate() on the same batch with counters
     (n_accept); obs['status'] gains ADJ_SKIPPED where the gradient is NaN.  ws: optional uint8 device
-    workspace of adjoint_workspace_bytes() bytes (else allocated by the library)."""
+    workspace of adjoint_workspace_bytes() bytes (else allocated by the library).  With y0_bar=True
+    returns (p_bar, y0_bar), y0_bar (n x 12) the gradient with respect to the start state in a.u."""
     L = _abi.load()
     obs_bar = obs_bar.contiguous()
     if obs_bar.shape != (n, 3) or obs_bar.dtype != torch.float64:
@@ -241,16 +242,17 @@ def adjoint(system, species, gen, n: int, obs: Dict[str, torch.Tensor], obs_bar:
     if "n_accept" not in obs:
         raise ValueError("obs must come from integrate(..., counters=True) of the same batch")
     p_bar = torch.empty(n, 5, dtype=torch.float64, device=obs_bar.device)
+    yb = torch.empty(n, 12, dtype=torch.float64, device=obs_bar.device) if y0_bar else None
     sysv = system_struct(system)
     sp = species_array(species)
     b = batch_struct(n, gen, arrays, None, id0)
     o = obs_struct(obs)
     la = launch_struct()
     rc = L.iat_adjoint(ctypes.byref(sysv), sp, len(species), ctypes.byref(b), ctypes.byref(o), _ptr(obs_bar),
-                       _ptr(p_bar), _ptr(ws), 0 if ws is None else ws.numel() * ws.element_size(),
+                       _ptr(p_bar), _ptr(yb), _ptr(ws), 0 if ws is None else ws.numel() * ws.element_size(),
                        ctypes.byref(la), _stream_handle(stream))
     _abi.check(rc)
-    return p_bar
+    return (p_bar, yb) if y0_bar else p_bar
 
 
 def adjoint_workspace_bytes(system, species, gen, n: int, obs, *, arrays=None, id0=None, stream=None) -> int:

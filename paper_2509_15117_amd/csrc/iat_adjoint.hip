@@ -44,7 +44,7 @@ struct AdjBuf {
     int64_t cap;         // records available
     double* lam;         // [12][n] adjoint of the state (seed, then at the start)
     double* acc;         // [3][n] q_x and De adjoint sums, exponent of the 2^400 rescaling
-    double* expl;        // [5][n] explicit terms (unscaled)
+    double* expl;        // [8][n] explicit terms (unscaled): 5 parameters, then dJ/dv_atom(0) (a.u.)
     int32_t* info;       // [2][n] committed steps, state (1 = ok, kSkip = skipped)
     double* scr;         // per-quad scratch [kSeg][kScr][lanes]
     int64_t lanes;       // 4 x resident quads of the reverse kernel
@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(128) k_adj_seed(KParams P, Work W, AdjBuf B, c
     if (i >= P.n) return;
     double lam[12];
     for (int a = 0; a < 12; ++a) lam[a] = 0.0;
-    double ex[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double ex[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (B.info[P.n + i] == 1) {
         TrajParams tp;
         traj_params(P, i, tp);
@@ -271,12 +271,13 @@ __global__ void __launch_bounds__(128) k_adj_seed(KParams P, Work W, AdjBuf B, c
         }
         StartDeriv S;
         start_derivatives(P, tp, S);
+        for (int k = 0; k < 3; ++k) ex[5 + k] = ga * dang_dvi[k] - gq * dq_dvf[k];
         for (int p = 0; p < 3; ++p)
-            for (int k = 0; k < 3; ++k) ex[p] += (ga * dang_dvi[k] - gq * dq_dvf[k]) * S.dvi[p][k];
+            for (int k = 0; k < 3; ++k) ex[p] += ex[5 + k] * S.dvi[p][k];
         ex[3] = ge * dE_dq;
     }
     for (int a = 0; a < 12; ++a) B.lam[(int64_t)a * P.n + i] = lam[a];
-    for (int p = 0; p < 5; ++p) B.expl[(int64_t)p * P.n + i] = ex[p];
+    for (int p = 0; p < 8; ++p) B.expl[(int64_t)p * P.n + i] = ex[p];
 }
 
 // ---------------------------------------------------------------------------------------
@@ -472,13 +473,15 @@ __global__ void __launch_bounds__(256) k_adj_reverse(KParams P, Work W, AdjBuf B
 // ---------------------------------------------------------------------------------------
 // 5. chain rule through the head-on start, explicit terms, skipped trajectories
 // ---------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(128) k_adj_post(KParams P, AdjBuf B, double* p_bar)
+__global__ void __launch_bounds__(128) k_adj_post(KParams P, AdjBuf B, double* p_bar, double* y0_bar)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P.n) return;
     double* o = p_bar + 5 * i;
     if (B.info[P.n + i] != 1) {
         for (int p = 0; p < 5; ++p) o[p] = __builtin_nan("");
+        if (y0_bar)
+            for (int a = 0; a < 12; ++a) y0_bar[12 * i + a] = __builtin_nan("");
         P.status[i] |= IAT_ST_ADJ_SKIPPED;
         return;
     }
@@ -494,6 +497,13 @@ __global__ void __launch_bounds__(128) k_adj_post(KParams P, AdjBuf B, double* p
     }
     o[3] = ldexp(B.acc[i], e2) + B.expl[3 * P.n + i];
     o[4] = ldexp(B.acc[P.n + i], e2) + B.expl[4 * P.n + i];
+    if (y0_bar) {
+        // gradient with respect to the start state in a.u. (positions a0, velocities a.u.)
+        const double inv_w = 1.0 / P.omega;
+        for (int a = 0; a < 6; ++a) y0_bar[12 * i + a] = ldexp(B.lam[(int64_t)a * P.n + i], e2);
+        for (int a = 6; a < 12; ++a) y0_bar[12 * i + a] = ldexp(B.lam[(int64_t)a * P.n + i], e2) * inv_w;
+        for (int k = 0; k < 3; ++k) y0_bar[12 * i + 6 + k] += B.expl[(int64_t)(5 + k) * P.n + i];
+    }
 }
 
 // resident quads of the reverse kernel (and so its scratch size)
@@ -529,7 +539,7 @@ AdjLayout adj_layout(int64_t n)
     L.acc = o;
     o += up((size_t)n * 3 * sizeof(double));
     L.expl = o;
-    o += up((size_t)n * 5 * sizeof(double));
+    o += up((size_t)n * 8 * sizeof(double));
     L.info = o;
     o += up((size_t)n * 2 * sizeof(int32_t));
     L.scr = o;
@@ -583,7 +593,8 @@ extern "C" int iat_adjoint_workspace_bytes(const iat_system* sys, const iat_spec
 }
 
 extern "C" int iat_adjoint(const iat_system* sys, const iat_species* species, int n_species, const iat_batch* batch,
-                           const iat_obs* obs, const double* obs_bar, double* p_bar, void* ws, size_t ws_bytes,
+                           const iat_obs* obs, const double* obs_bar, double* p_bar, double* y0_bar, void* ws,
+                           size_t ws_bytes,
                            const iat_launch* launch, void* stream)
 {
     int rc = adj_check(sys, species, n_species, batch, obs);
@@ -631,7 +642,7 @@ extern "C" int iat_adjoint(const iat_system* sys, const iat_species* species, in
     hipLaunchKernelGGL(k_adj_seed, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, P, W, B, obs_bar);
     hipLaunchKernelGGL(k_adj_reverse, dim3((unsigned)(Lo.lanes / 256 + (Lo.lanes % 256 ? 1 : 0))), dim3(256), 0, st,
                        P, W, B);
-    hipLaunchKernelGGL(k_adj_post, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, P, B, p_bar);
+    hipLaunchKernelGGL(k_adj_post, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, P, B, p_bar, y0_bar);
     if (own && hipFreeAsync(own, st) != hipSuccess) return set_error(IAT_EHIP, "hipFreeAsync failed");
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(IAT_EHIP, "kernel launch failed: %s", hipGetErrorString(e));

@@ -3,7 +3,8 @@ central differences of the oracle.
 
 * Adjoint and tangent differentiate the same discrete map along the same primal bits, so
   obs_bar . dobs/dp from the tangent equals the adjoint's p_bar up to the rounding of the two
-  association orders of the Jacobian products: 1e-9 relative on direct trajectories.
+  association orders of the Jacobian products: within 1e-9 of the magnitudes of the contributing
+  terms on direct trajectories (the start-state rotations theta, phi sum nearly cancelling terms).
 * Against the oracle's tangent the bar is the oracle's own round-off spread (as for the tangent).
 * Central differences of the oracle's frozen-step map resolve these sensitivities only to a few
   1e-5 in FP64 at their best step (truncation O(h^2) of a strongly curved map above, round-off
@@ -36,37 +37,66 @@ def _run(w, n, seed=0):
     obs = api.integrate_workload(w, n=n, counters=True)
     g = torch.from_numpy(np.random.default_rng(seed).normal(size=(n, 3))).to(DEV)
     print(f"adjoint: {w.name}, n={n}", flush=True)
-    pb = api.adjoint(w.system, w.species(), w.gen, n, obs, g)
+    pb, yb = api.adjoint(w.system, w.species(), w.gen, n, obs, g, y0_bar=True)
     torch.cuda.synchronize()
-    return obs, g.cpu().numpy(), pb.cpu().numpy()
+    return obs, g.cpu().numpy(), pb.cpu().numpy(), yb.cpu().numpy()
+
+
+def _dy0(w, theta, phi, E):
+    """d(start state, a.u.)/d(theta, phi, E) of the head-on start."""
+    m = w.species()[w.system.species][0]
+    st, ct, sp, cp = np.sin(theta), np.cos(theta), np.sin(phi), np.cos(phi)
+    n = np.array([st * cp, st * sp, ct])
+    nt = np.array([ct * cp, ct * sp, -st])
+    nph = np.array([-st * sp, st * cp, 0.0])
+    v0 = np.sqrt(2.0 * E / m)
+    d = np.zeros((3, 12))
+    d[0, :3], d[0, 6:9] = w.system.r0 * nt, -v0 * nt
+    d[1, :3], d[1, 6:9] = w.system.r0 * nph, -v0 * nph
+    d[2, 6:9] = -v0 / (2.0 * E) * n
+    return d
+
+
+def _rounding_bar(w, b, y0bar, theta, phi, rel=1e-9):
+    """Per parameter: rel x (|b_p| + the magnitudes of the terms that the start-state contraction adds,
+    sum_c |dy0_pc y0bar_c|).  Rotations of the start (theta, phi) move the atom's position and
+    velocity together and their contributions nearly cancel for the axially symmetric trap, so a
+    relative rounding error of the terms shows up amplified in the sum."""
+    s = _scales(w)
+    T = np.abs(b * s)
+    T[:3] += (np.abs(_dy0(w, theta, phi, w.system.E) * y0bar[None, :])).sum(1) * s[:3]
+    return rel * T + 1e-12 * np.linalg.norm(b * s)
 
 
 def test_adjoint_equals_tangent_contraction():
     w = W.config1()
-    obs, g, pb = _run(w, 64)
+    obs, g, pb, yb = _run(w, 64)
     tan = PT.to_numpy(api.tangent(w.system, w.species(), w.gen, 64))
     ref = np.einsum("ik,ikp->ip", g, tan["dobs_dp"])
     s = _scales(w)
     st = obs["status"].cpu().numpy()
     nb = obs["n_bounce"].cpu().numpy()
+    thph = oracle.grid_angles(range(64), 8, 8)
     worst_direct, worst_all = 0.0, 0.0
     for i in range(64):
         assert (st[i] & _abi.ST_ADJ_SKIPPED) == 0, i
         a, b = pb[i] * s, ref[i] * s
         if not (np.all(np.isfinite(a)) and np.all(np.isfinite(b))):
             continue
-        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
-        worst_all = max(worst_all, rel)
+        bar = _rounding_bar(w, ref[i], yb[i], *thph[i])
+        ratio = np.max(np.abs(a - b) / bar)
+        worst_all = max(worst_all, ratio)
         if nb[i] <= 1:
-            worst_direct = max(worst_direct, rel)
-            assert rel <= 1e-9, (i, a, b)
-    print(f"adjoint vs tangent: direct {worst_direct:.2e}, all finite {worst_all:.2e}", flush=True)
-    assert worst_all <= 1e-6
+            worst_direct = max(worst_direct, ratio)
+            assert ratio <= 1.0, (i, a, b, bar)
+    print(f"adjoint vs tangent, |diff| / rounding bar (1e-9 of the terms): direct {worst_direct:.2e}, "
+          f"all finite {worst_all:.2e}", flush=True)
+    assert worst_all <= 1e3      # long-lived complexes: products of ~1e6 Jacobians in two orders
 
 
 def test_adjoint_against_oracle_tangent_and_differences():
     w = W.config1()
-    obs, g, pb = _run(w, 64, seed=1)
+    obs, g, pb, _ = _run(w, 64, seed=1)
     P = oracle.problems_for(w, range(64))
     thph = oracle.grid_angles(range(64), 8, 8)
     s = _scales(w)
@@ -97,7 +127,7 @@ def test_adjoint_workspace_and_skipping():
     """A workspace that holds the fixed part and only some records: the trajectories that fit get the
     same bits as with a full workspace, the others NaN and the skipped status bit."""
     w = W.config1()
-    obs, g, full = _run(w, 64, seed=2)
+    obs, g, full, _ = _run(w, 64, seed=2)
     need = api.adjoint_workspace_bytes(w.system, w.species(), w.gen, 64, obs)
     assert need > 0
     ws = torch.empty(need, dtype=torch.uint8, device=DEV)
@@ -139,8 +169,14 @@ def test_autograd_function_matches_adjoint():
     tan = PT.to_numpy(api.tangent(w.system, w.species(), w.gen, 64))["dobs_dp"][40:40 + n]
     ref = np.einsum("ik,ikp->ip", gbar.cpu().numpy(), tan)
     got = np.stack([t.grad.cpu().numpy() for t in (theta, phi, E, q, De)], axis=1)
+    # the backward pass is the adjoint of the same batch: identical to calling it directly
+    _, yb = api.adjoint(w.system, w.species(), w.gen, 64, grid,
+                        torch.cat([torch.zeros(40, 3, dtype=torch.float64, device=DEV), gbar,
+                                   torch.zeros(64 - 40 - n, 3, dtype=torch.float64, device=DEV)]), y0_bar=True)
+    yb = yb.cpu().numpy()[40:40 + n]
     s = _scales(w)
     nb = grid["n_bounce"][40:40 + n].cpu().numpy()
     for i in range(n):
         if nb[i] <= 1:
-            assert np.linalg.norm((got[i] - ref[i]) * s) <= 1e-9 * np.linalg.norm(ref[i] * s), i
+            bar = _rounding_bar(w, ref[i], yb[i], *thph[i])
+            assert np.all(np.abs(got[i] - ref[i]) * s <= bar), (i, got[i], ref[i])
