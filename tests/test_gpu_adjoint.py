@@ -3,10 +3,13 @@ central differences of the oracle.
 
 * Adjoint and tangent differentiate the same discrete map along the same primal bits, so
   obs_bar . dobs/dp from the tangent equals the adjoint's p_bar up to the rounding of the two
-  association orders of the Jacobian products: within 1e-8 of the magnitudes of the contributing
-  terms on direct trajectories (the start-state rotations theta, phi sum nearly cancelling terms).
-  The two orders differ by a few 1e-9 there: the collision amplifies the rounding of the ~4000
-  step Jacobians by the condition of the stability matrix (singular values from 1e-3 to 1e3).
+  association orders of the Jacobian products: within 1e-7 of the magnitudes of the contributing
+  terms on direct trajectories (the start-state rotations theta, phi sum nearly cancelling terms,
+  and q_x collects stage terms that oscillate with the RF phase).  The two orders differ by up to
+  ~2e-8 there: the collision amplifies the rounding of the ~4000 step Jacobians by the condition
+  of the stability matrix (singular values from 1e-3 to 1e3); a wrong term would show at 1e-3..1.
+* The trap is axially symmetric, so d/dphi vanishes exactly: the adjoint returns it below 1e-10 of
+  its terms (the tangent's own rounding leaves ~1e-9).
 * Against the oracle's tangent the bar is the oracle's own round-off spread (as for the tangent).
 * Central differences of the oracle's frozen-step map resolve these sensitivities only to a few
   1e-5 in FP64 at their best step (truncation O(h^2) of a strongly curved map above, round-off
@@ -59,7 +62,7 @@ def _dy0(w, theta, phi, E):
     return d
 
 
-def _rounding_bar(w, b, y0bar, theta, phi, rel=1e-8):
+def _rounding_bar(w, b, y0bar, theta, phi, rel=1e-7):
     """Per parameter: rel x (|b_p| + the magnitudes of the terms that the start-state contraction adds,
     sum_c |dy0_pc y0bar_c|).  Rotations of the start (theta, phi) move the atom's position and
     velocity together and their contributions nearly cancel for the axially symmetric trap, so a
@@ -87,11 +90,13 @@ def test_adjoint_equals_tangent_contraction():
             continue
         bar = _rounding_bar(w, ref[i], yb[i], *thph[i])
         ratio = np.max(np.abs(a - b) / bar)
+        # axial symmetry: the azimuthal derivative vanishes up to the rounding of its terms
+        assert abs(a[1]) <= 1e-10 * (_rounding_bar(w, ref[i], yb[i], *thph[i], rel=1.0)[1]), (i, a[1])
         worst_all = max(worst_all, ratio)
         if nb[i] <= 1:
             worst_direct = max(worst_direct, ratio)
             assert ratio <= 1.0, (i, a, b, bar)
-    print(f"adjoint vs tangent, |diff| / rounding bar (1e-8 of the terms): direct {worst_direct:.2e}, "
+    print(f"adjoint vs tangent, |diff| / rounding bar (1e-7 of the terms): direct {worst_direct:.2e}, "
           f"all finite {worst_all:.2e}", flush=True)
     assert worst_all <= 1e3      # long-lived complexes: products of ~1e6 Jacobians in two orders
 
