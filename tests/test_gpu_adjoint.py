@@ -93,6 +93,8 @@ def test_adjoint_equals_tangent_contraction():
         worst_all = max(worst_all, ratio)
         if nb[i] <= 1:
             worst_direct = max(worst_direct, ratio)
+            print(f"direct {i}: |diff|/bar per parameter {np.array2string(np.abs(a - b) / bar, precision=2)}",
+                  flush=True)
             assert ratio <= 1.0, (i, a, b, bar)
             # axial symmetry: the azimuthal derivative vanishes up to the rounding of its terms
             assert abs(a[1]) <= 1e-10 * (_rounding_bar(w, ref[i], yb[i], *thph[i], rel=1.0)[1]), (i, a[1])
