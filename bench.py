@@ -29,7 +29,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="grid1024", choices=["grid1024", "grid8", "sweep"])
+    ap.add_argument("--workload", default="grid1024", choices=["grid1024", "grid8", "sweep", "stream"],
+                    help="grid1024: the 1024^2 head-on grid (one batch); sweep: the 1.2e7-trajectory 225-cell "
+                         "sweep with per-cell reductions; stream: the 1e8-trajectory Li/K/Cs sweep keeping only "
+                         "histograms (both in chunks over several streams)")
+    ap.add_argument("--chunk", type=int, default=0, help="ids per chunk (sweep: 2^21, stream: 2^22)")
+    ap.add_argument("--streams", type=int, default=4, help="streams the chunks are spread over")
+    ap.add_argument("--n", type=int, default=0, help="run only the first N ids of the workload")
     ap.add_argument("--kernel", default="persistent", choices=["persistent", "plain"])
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
@@ -45,12 +51,94 @@ def parse():
 
 def workload(name):
     import workloads as W
-    if name == "grid1024":
-        return W.config2()
-    if name == "grid8":
-        return W.config1()
-    w = W.config3()
-    return w
+    return {"grid1024": W.config2, "grid8": W.config1, "sweep": W.config3, "stream": W.config5}[name]()
+
+
+def chunked_job(api, torch, w, n, args, stats, kernel):
+    """One pass over ids [0, n) in chunks on several streams, reductions on the device; HIP events on the
+    current stream, which joins the side streams at the end of the pass."""
+    chunk = args.chunk or (1 << 21 if args.workload == "sweep" else 1 << 22)
+    cur = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(cur)
+    res = api.run_chunks(w, n=n, chunk=chunk, n_streams=args.streams, kernel=kernel,
+                         cells=(w.gen.kind == "sweep" and args.workload == "sweep"),
+                         hist=(args.workload == "stream"), stats=stats)
+    e1.record(cur)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3, res, chunk
+
+
+def kernel_profile(api, torch, w, n, kernel):
+    """Event-timed phases of one single-stream call on ids [0, n): the per-kernel roofline figures."""
+    import ctypes
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    out = api.alloc_obs(n, torch.device("cuda", 0), counters=False)
+    ms = (ctypes.c_float * 4)()
+    api.integrate_workload(w, n=n, out=out, stats=stats, kernel_ms=ms, kernel=kernel)
+    s = stats.cpu().tolist()
+    return list(ms), s
+
+
+def main_chunked(args):
+    import torch
+    from paper_2509_15117_amd import api
+    torch.cuda.set_device(0)
+    w = workload(args.workload)
+    n = args.n or w.n
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    for _ in range(args.warmup):
+        chunked_job(api, torch, w, n, args, None, args.kernel)
+    secs, res = 0.0, None
+    for k in range(args.steps):
+        stats_k = stats if k == 0 else None
+        t, res, chunk = chunked_job(api, torch, w, n, args, stats_k, args.kernel)
+        secs += t
+        print(f"[bench] pass {k + 1}/{args.steps}: {t:.2f} s", file=sys.stderr, flush=True)
+    K = args.steps
+    s = stats.cpu().tolist()
+    traj_s = n * K / secs
+    stages_s = s[0] / (secs / K)
+    # per-kernel figures from one event-timed single-stream call on the first chunk
+    ms, ks = kernel_profile(api, torch, w, min(n, chunk), args.kernel)
+    main_name = "k_integrate_persistent" if args.kernel == "persistent" else "k_integrate_plain"
+    kernels = []
+    for name, secs_k, rhs in ((main_name, ms[1] / 1e3, ks[0] - ks[6]), ("k_integrate_tail", ms[2] / 1e3, ks[6])):
+        if secs_k > 0:
+            tf = FLOP_PER_RHS * rhs / secs_k / 1e12
+            kernels.append({"kernel": name, "avg_launch_ms": secs_k * 1e3, "rhs_per_launch": rhs,
+                            "flop_per_launch": FLOP_PER_RHS * rhs, "achieved": tf, "frac": tf / FP64_PEAK_TFLOPS,
+                            "traffic": traffic_bytes(args.traffic_file, w.name, name),
+                            "launch": f"first chunk of {min(n, chunk)} ids, one stream"})
+    dom = max(kernels, key=lambda k: k["avg_launch_ms"])
+    out = {
+        "metric": "trajectories/s + RK stages/s (FP64, rtol 1e-10): refill kernel vs plain, % FP64 peak",
+        "value": traj_s, "unit": "trajectories/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": secs * 1e3 / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "trajectories": n, "chunk": chunk, "streams": args.streams,
+                   "kernel": args.kernel, "rtol": w.system.rtol, "atol": w.system.atol,
+                   "reductions": "per-cell sums" if args.workload == "sweep" else "W0 and heating histograms"},
+        "rk_stages_per_s": stages_s, "accepted_steps_per_s": s[1] / (secs / K),
+        "fp64_frac_peak": FLOP_PER_RHS * stages_s / (FP64_PEAK_TFLOPS * 1e12),
+        "active_lane_fraction": s[5] / max(s[4], 1),
+        "roofline": {"bound": "alu", "kernel": dom["kernel"], "achieved": dom["achieved"], "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": dom["frac"], "traffic": dom["traffic"],
+                     "avg_launch_ms": dom["avg_launch_ms"], "flop_per_launch": dom["flop_per_launch"]},
+        "kernels": kernels,
+    }
+    if args.workload == "sweep" and res is not None:
+        c = res["cells"].cpu()
+        out["p_complex_range"] = [float((c[:, 1] / c[:, 0]).min()), float((c[:, 1] / c[:, 0]).max())]
+    if not args.no_plain and args.kernel != "plain":
+        m = min(n, 4 * chunk)
+        tp, _, _ = chunked_job(api, torch, w, m, args, None, "plain")
+        tr, _, _ = chunked_job(api, torch, w, m, args, None, "persistent")
+        out["plain"] = {"trajectories_per_s": m / tp, "sample": f"first {m} ids", "refill_same_sample": m / tr}
+        out["speedup_vs_plain"] = tp / tr
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w.with_n(n), args.cpu_seconds)
+    print(json.dumps(out), flush=True)
 
 
 def timed_runs(api, torch, w, out, stats, steps, warmup, **launch):
@@ -153,6 +241,12 @@ def main():
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy, 3)
         return
+    if args.workload in ("sweep", "stream"):
+        if args.gpus != 1:
+            print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",
+                              "n_gpus": args.gpus}))
+            sys.exit(2)
+        return main_chunked(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))

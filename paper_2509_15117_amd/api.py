@@ -294,3 +294,46 @@ class ScatteringObservables(torch.autograd.Function):
         arrays = dict(zip(ctx.keys, ctx.saved_tensors))
         p_bar = adjoint(system, species, gen, n, ctx.obs, grad.to(torch.float64).contiguous(), arrays=arrays)
         return p_bar[:, 0], p_bar[:, 1], p_bar[:, 2], p_bar[:, 3], p_bar[:, 4], None, None, None, None
+
+
+def run_chunks(w, *, n: Optional[int] = None, chunk: int = 1 << 22, n_streams: int = 4, kernel="persistent",
+               cells: bool = False, hist: bool = False, stats: Optional[torch.Tensor] = None, **launch):
+    """Integrate ids [0, n) of a workloads.Workload in chunks of `chunk` ids spread round-robin over
+    `n_streams` streams (default priority), reducing each chunk on its stream: per-cell sums (cells=True,
+    sweeps) and the W0 / heating histograms (hist=True).  Only the reductions are kept.  While one
+    chunk's long-lived complexes finish in its tail kernel, the next chunks run on the other streams.
+    Returns {'cells': (n_cells, 5), 'hist': flat histogram} (device tensors, summed over streams)."""
+    n = w.n if n is None else n
+    dev = torch.device("cuda", torch.cuda.current_device())
+    cur = torch.cuda.current_stream()
+    streams = [torch.cuda.Stream(device=dev) for _ in range(max(1, n_streams))]
+    m = min(chunk, n)
+    bufs = [alloc_obs(m, dev, counters=False) for _ in streams]
+    slots = len(w.gen.species) if w.gen.kind == "sweep" else 1
+    c_out = [torch.zeros(n_cells(w.gen), 5, dtype=torch.float64, device=dev) for _ in streams] if cells else None
+    h_out = ([torch.zeros(slots * 2 * _abi.W0_BINS + _abi.HEAT_BINS, dtype=torch.float64, device=dev)
+              for _ in streams] if hist else None)
+    for s in streams:
+        s.wait_stream(cur)
+    for c, id0 in enumerate(range(0, n, chunk)):
+        k = c % len(streams)
+        cnt = min(chunk, n - id0)
+        obs = {key: v[:cnt] for key, v in bufs[k].items()}
+        integrate(w.system, w.species(), w.gen, cnt, id0=id0, out=obs, stream=streams[k], kernel=kernel, stats=stats,
+                  **launch)
+        if cells:
+            reduce_cells(w.system, w.species(), w.gen, cnt, obs, id0=id0, out=c_out[k], stream=streams[k])
+        if hist:
+            reduce_hist(w.system, w.species(), w.gen, cnt, obs, id0=id0, out=h_out[k], stream=streams[k])
+    for s in streams:
+        cur.wait_stream(s)
+    res = {}
+    if cells:
+        res["cells"] = torch.stack(c_out).sum(0)
+    if hist:
+        res["hist"] = torch.stack(h_out).sum(0)
+    for b in bufs:               # the buffers were used on the side streams
+        for v in b.values():
+            for s in streams:
+                v.record_stream(s)
+    return res
