@@ -61,9 +61,15 @@ def chunked_job(api, torch, w, n, args, stats, kernel):
     cur = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(cur)
+    t0 = time.perf_counter()
+
+    def progress(c, nc):
+        print(f"[bench] {kernel}: chunk {c + 1}/{nc} done at {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+              flush=True)
+
     res = api.run_chunks(w, n=n, chunk=chunk, n_streams=args.streams, kernel=kernel,
                          cells=(w.gen.kind == "sweep" and args.workload == "sweep"),
-                         hist=(args.workload == "stream"), stats=stats)
+                         hist=(args.workload == "stream"), stats=stats, progress=progress)
     e1.record(cur)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / 1e3, res, chunk
@@ -100,7 +106,9 @@ def main_chunked(args):
     traj_s = n * K / secs
     stages_s = s[0] / (secs / K)
     # per-kernel figures from one event-timed single-stream call on the first chunk
+    print(f"[bench] kernel profile of the first {min(n, chunk)} ids", file=sys.stderr, flush=True)
     ms, ks = kernel_profile(api, torch, w, min(n, chunk), args.kernel)
+    print(f"[bench] phases ms {[round(x, 1) for x in ms]}", file=sys.stderr, flush=True)
     main_name = "k_integrate_persistent" if args.kernel == "persistent" else "k_integrate_plain"
     kernels = []
     for name, secs_k, rhs in ((main_name, ms[1] / 1e3, ks[0] - ks[6]), ("k_integrate_tail", ms[2] / 1e3, ks[6])):
@@ -131,12 +139,17 @@ def main_chunked(args):
         c = res["cells"].cpu()
         out["p_complex_range"] = [float((c[:, 1] / c[:, 0]).min()), float((c[:, 1] / c[:, 0]).max())]
     if not args.no_plain and args.kernel != "plain":
-        m = min(n, 4 * chunk)
-        tp, _, _ = chunked_job(api, torch, w, m, args, None, "plain")
-        tr, _, _ = chunked_job(api, torch, w, m, args, None, "persistent")
-        out["plain"] = {"trajectories_per_s": m / tp, "sample": f"first {m} ids", "refill_same_sample": m / tr}
+        # plain vs refill on the same sample: the first 2^20 ids, one chunk per stream
+        m = min(n, 1 << 20)
+        sub = argparse.Namespace(**vars(args))
+        sub.chunk = max(1, m // max(1, args.streams))
+        tp, _, _ = chunked_job(api, torch, w, m, sub, None, "plain")
+        tr, _, _ = chunked_job(api, torch, w, m, sub, None, "persistent")
+        out["plain"] = {"trajectories_per_s": m / tp, "sample": f"first {m} ids in {args.streams} chunks",
+                        "refill_same_sample": m / tr}
         out["speedup_vs_plain"] = tp / tr
     if not args.no_cpu:
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w.with_n(n), args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

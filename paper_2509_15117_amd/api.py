@@ -297,12 +297,14 @@ class ScatteringObservables(torch.autograd.Function):
 
 
 def run_chunks(w, *, n: Optional[int] = None, chunk: int = 1 << 22, n_streams: int = 4, kernel="persistent",
-               cells: bool = False, hist: bool = False, stats: Optional[torch.Tensor] = None, **launch):
+               cells: bool = False, hist: bool = False, stats: Optional[torch.Tensor] = None, progress=None,
+               **launch):
     """Integrate ids [0, n) of a workloads.Workload in chunks of `chunk` ids spread round-robin over
     `n_streams` streams (default priority), reducing each chunk on its stream: per-cell sums (cells=True,
     sweeps) and the W0 / heating histograms (hist=True).  Only the reductions are kept.  While one
     chunk's long-lived complexes finish in its tail kernel, the next chunks run on the other streams.
-    Returns {'cells': (n_cells, 5), 'hist': flat histogram} (device tensors, summed over streams)."""
+    Returns {'cells': (n_cells, 5), 'hist': flat histogram} (device tensors, summed over streams).
+    progress(c, n_chunks): called on the host as chunk c completes (in chunk order)."""
     n = w.n if n is None else n
     dev = torch.device("cuda", torch.cuda.current_device())
     cur = torch.cuda.current_stream()
@@ -315,6 +317,7 @@ def run_chunks(w, *, n: Optional[int] = None, chunk: int = 1 << 22, n_streams: i
               for _ in streams] if hist else None)
     for s in streams:
         s.wait_stream(cur)
+    done = []
     for c, id0 in enumerate(range(0, n, chunk)):
         k = c % len(streams)
         cnt = min(chunk, n - id0)
@@ -325,6 +328,13 @@ def run_chunks(w, *, n: Optional[int] = None, chunk: int = 1 << 22, n_streams: i
             reduce_cells(w.system, w.species(), w.gen, cnt, obs, id0=id0, out=c_out[k], stream=streams[k])
         if hist:
             reduce_hist(w.system, w.species(), w.gen, cnt, obs, id0=id0, out=h_out[k], stream=streams[k])
+        if progress is not None:
+            ev = torch.cuda.Event()
+            ev.record(streams[k])
+            done.append(ev)
+    for c, ev in enumerate(done):
+        ev.synchronize()
+        progress(c, len(done))
     for s in streams:
         cur.wait_stream(s)
     res = {}
