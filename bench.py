@@ -33,7 +33,7 @@ def parse():
                     help="grid1024: the 1024^2 head-on grid (one batch); sweep: the 1.2e7-trajectory 225-cell "
                          "sweep with per-cell reductions; stream: the 1e8-trajectory Li/K/Cs sweep keeping only "
                          "histograms (both in chunks over several streams)")
-    ap.add_argument("--chunk", type=int, default=0, help="ids per chunk (sweep: 2^21, stream: 2^22)")
+    ap.add_argument("--chunk", type=int, default=0, help="ids per chunk (default: the job split evenly over the streams)")
     ap.add_argument("--streams", type=int, default=4, help="streams the chunks are spread over")
     ap.add_argument("--n", type=int, default=0, help="run only the first N ids of the workload")
     ap.add_argument("--kernel", default="persistent", choices=["persistent", "plain"])
@@ -57,7 +57,9 @@ def workload(name):
 def chunked_job(api, torch, w, n, args, stats, kernel):
     """One pass over ids [0, n) in chunks on several streams, reductions on the device; HIP events on the
     current stream, which joins the side streams at the end of the pass."""
-    chunk = args.chunk or (1 << 21 if args.workload == "sweep" else 1 << 22)
+    # default: one chunk per stream, so every chunk's main kernel and long-lived tail run concurrently
+    # (HBM holds a 1e8-trajectory job: ~240 B of work buffer and outputs per trajectory)
+    chunk = args.chunk or -(-n // max(1, args.streams))
     cur = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(cur)
