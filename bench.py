@@ -34,7 +34,7 @@ def parse():
                          "sweep with per-cell reductions; stream: the 1e8-trajectory Li/K/Cs sweep keeping only "
                          "histograms (both in chunks over several streams)")
     ap.add_argument("--chunk", type=int, default=0, help="ids per chunk (default: the job split evenly over the streams)")
-    ap.add_argument("--streams", type=int, default=4, help="streams the chunks are spread over")
+    ap.add_argument("--streams", type=int, default=2, help="streams the chunks are spread over")
     ap.add_argument("--n", type=int, default=0, help="run only the first N ids of the workload")
     ap.add_argument("--kernel", default="persistent", choices=["persistent", "plain"])
     ap.add_argument("--block", type=int, default=0)

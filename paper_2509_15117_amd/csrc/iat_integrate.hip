@@ -22,7 +22,7 @@
 namespace iat {
 
 constexpr int64_t kDefaultBudget = 20000;        // attempted steps before a trajectory moves to 4 lanes
-constexpr int64_t kMaxSuspended = 1 << 21;       // continuation records per call
+constexpr int64_t kMaxSuspended = 1 << 23;       // continuation records per call (248 B each)
 
 __device__ __forceinline__ uint64_t wave_sum(uint64_t v)
 {
