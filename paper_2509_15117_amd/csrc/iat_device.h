@@ -352,20 +352,30 @@ __device__ __forceinline__ void small_sincos(double d, double& c, double& s)
 // sin and cos of an RF phase 0 <= x < 1.6e6: Cody-Waite reduction x = k pi/2 + r with pi/2
 // split into P1 + P2 + P3 (33, 33 and 53 significant bits, so k P1 and k P2 are exact for
 // |k| < 2^20), then the Maclaurin polynomials on |r| <= pi/4 and the quadrant k mod 4.
-__device__ __forceinline__ void phase_sincos(double x, double& s, double& c)
+__device__ __forceinline__ double phase_reduce(double x, double& k)
 {
     constexpr double kTwoOverPi = 0.63661977236758134308;
     constexpr double P1 = 0x1.921fb54400000p+0, P2 = 0x1.0b4611a600000p-34, P3 = 0x1.3198a2e037073p-69;
-    const double k = rint(x * kTwoOverPi);
+    k = rint(x * kTwoOverPi);
     double r = fma(-k, P1, x);
     r = fma(-k, P2, r);
-    r = fma(-k, P3, r);
-    double cr, sr;
-    small_sincos(r, cr, sr);
+    return fma(-k, P3, r);
+}
+// sin, cos of x = k pi/2 + r from cos r, sin r
+__device__ __forceinline__ void phase_quadrant(double k, double cr, double sr, double& s, double& c)
+{
     const int q = ((int)k) & 3;
     const double a = (q & 1) ? cr : sr, b = (q & 1) ? sr : cr;   // sin, cos up to sign
     s = (q & 2) ? -a : a;
     c = ((q + 1) & 2) ? -b : b;
+}
+__device__ __forceinline__ void phase_sincos(double x, double& s, double& c)
+{
+    double k;
+    const double r = phase_reduce(x, k);
+    double cr, sr;
+    small_sincos(r, cr, sr);
+    phase_quadrant(k, cr, sr, s, c);
 }
 
 // en^(-1/5) for en >= 1e-4: single-precision estimate from the hardware log2/exp2, refined by
@@ -383,12 +393,14 @@ __device__ __forceinline__ double inv_fifth_root(double en)
     return y;
 }
 
+// cos(theta + d) from cos/sin(theta) and cos/sin(d)
+__device__ __forceinline__ double cos_comb(double cb, double sb, double c, double s) { return cb * c - sb * s; }
 // cos(theta + d) from cos/sin(theta) and the stage offset d
 __device__ __forceinline__ double cos_shift(double cb, double sb, double d)
 {
     double c, s;
     small_sincos(d, c, s);
-    return cb * c - sb * s;
+    return cos_comb(cb, sb, c, s);
 }
 
 // Cosines of the RF phase at the stage times tau + c_s h (s = 2..6; stage 7 shares c = 1).
@@ -803,6 +815,30 @@ __device__ __forceinline__ int quad_or(int v)
     return v | __builtin_amdgcn_mov_dpp(v, x2, 0xF, 0xF, false);
 }
 
+// Stage cosines for the four-lane form: the values of stage_cos, with its six polynomial
+// evaluations (the phase remainder and the five stage offsets) shared out over the quad's lanes
+// in two rounds and gathered with quad moves.
+__device__ __forceinline__ StageCos stage_cos4(double tau, double phase0, double h)
+{
+    const int l = __lane_id() & 3;
+    double k;
+    const double r = phase_reduce(tau + phase0, k);
+    const double a1 = l == 0 ? r : (l == 1 ? c2 * h : (l == 2 ? c3 * h : c4 * h));
+    const double a2 = (l & 1) ? h : c5 * h;
+    double cA, sA, cB, sB;
+    small_sincos(a1, cA, sA);
+    small_sincos(a2, cB, sB);
+    double sb, cb;
+    phase_quadrant(k, quad_bcast<0>(cA), quad_bcast<0>(sA), sb, cb);
+    StageCos C;
+    C.c2 = cos_comb(cb, sb, quad_bcast<1>(cA), quad_bcast<1>(sA));
+    C.c3 = cos_comb(cb, sb, quad_bcast<2>(cA), quad_bcast<2>(sA));
+    C.c4 = cos_comb(cb, sb, quad_bcast<3>(cA), quad_bcast<3>(sA));
+    C.c5 = cos_comb(cb, sb, quad_bcast<0>(cB), quad_bcast<0>(sB));
+    C.c6 = cos_comb(cb, sb, quad_bcast<1>(cB), quad_bcast<1>(sB));
+    return C;
+}
+
 struct Traj4 {
     double xa, xi, va, vi, F1a, F1i;   // this lane's axis
     Scal S;
@@ -865,7 +901,7 @@ __device__ __forceinline__ int traj4_step(const KParams& P, Traj4& T, double& h_
     const bool exiting = T.S.mode != 0;
     const int k = quad_axis();
     const double hh = h * h;
-    const StageCos C = stage_cos(T.S.tau, T.L.phase0, h);
+    const StageCos C = stage_cos4(T.S.tau, T.L.phase0, h);
     double F2a, F2i, F3a, F3i, F4a, F4i, F5a, F5i, F6a, F6i;
     accel4(P, T.L, k, C.c2, stage2(T.xa, T.va, h), stage2(T.xi, T.vi, h), F2a, F2i);
     accel4(P, T.L, k, C.c3, stage3(T.xa, T.va, h, hh, T.F1a), stage3(T.xi, T.vi, h, hh, T.F1i), F3a, F3i);

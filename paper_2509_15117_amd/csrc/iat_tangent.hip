@@ -85,7 +85,7 @@ __device__ __forceinline__ void tan4_advance(const KParams& P, Traj4& T, Tan4& D
     const bool exiting = T.S.mode != 0;
     const int k = quad_axis();
     const double hh = h * h;
-    const StageCos C = stage_cos(T.S.tau, T.L.phase0, h);
+    const StageCos C = stage_cos4(T.S.tau, T.L.phase0, h);
     double F2a, F2i, F3a, F3i, F4a, F4i, F5a, F5i, F6a, F6i;
     double G2a, G2i, G3a, G3i, G4a, G4i, G5a, G5i, G6a, G6i;
     const double ff = D.ffac;
