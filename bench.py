@@ -29,10 +29,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="grid1024", choices=["grid1024", "grid8", "sweep", "stream"],
+    ap.add_argument("--workload", default="grid1024",
+                    choices=["grid1024", "grid8", "sweep", "stream", "tangent", "adjoint"],
                     help="grid1024: the 1024^2 head-on grid (one batch); sweep: the 1.2e7-trajectory 225-cell "
                          "sweep with per-cell reductions; stream: the 1e8-trajectory Li/K/Cs sweep keeping only "
-                         "histograms (both in chunks over several streams)")
+                         "histograms (both in chunks over several streams); tangent / adjoint: the 512^2 "
+                         "differentiation grid")
+    ap.add_argument("--autotune", default="", metavar="CACHE.json",
+                    help="pick block / refill / step budget by timing candidates on 2^16 ids (cached)")
     ap.add_argument("--chunk", type=int, default=0, help="ids per chunk (default: the job split evenly over the streams)")
     ap.add_argument("--streams", type=int, default=2, help="streams the chunks are spread over")
     ap.add_argument("--n", type=int, default=0, help="run only the first N ids of the workload")
@@ -51,7 +55,67 @@ def parse():
 
 def workload(name):
     import workloads as W
-    return {"grid1024": W.config2, "grid8": W.config1, "sweep": W.config3, "stream": W.config5}[name]()
+    return {"grid1024": W.config2, "grid8": W.config1, "sweep": W.config3, "stream": W.config5,
+            "tangent": W.config4, "adjoint": W.config4}[name]()
+
+
+# algorithmic FLOP of the differentiation (canonical count): per attempted step of the
+# primal 966; per tangent column and step 6 x 35 + 552 = 762; the adjoint per committed step recomputes
+# the step (966) and applies one transposed column (762), after a checkpointing forward pass (966).
+FLOP_PER_STEP, FLOP_PER_COLUMN_STEP = 966, 762
+
+
+def main_diff(args):
+    import numpy as np
+    import torch
+    from paper_2509_15117_amd import api
+    torch.cuda.set_device(0)
+    w = workload(args.workload)
+    n = args.n or w.n
+    cur = torch.cuda.current_stream()
+    obs = api.integrate_workload(w, n=n, counters=True)       # primal counts (and the adjoint's input)
+    torch.cuda.synchronize()
+    rhs = float(obs["n_rhs"].sum())
+    acc = float(obs["n_accept"].sum())
+    steps = rhs / 6.0
+    print(f"[bench] primal: {rhs:.3e} RHS evaluations", file=sys.stderr, flush=True)
+    times = []
+    for k in range(args.warmup + args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(cur)
+        if args.workload == "tangent":
+            api.tangent(w.system, w.species(), w.gen, n)
+            flop = steps * (FLOP_PER_STEP + 14 * FLOP_PER_COLUMN_STEP)
+            kname = "k_tangent"
+        else:
+            g = torch.from_numpy(np.random.default_rng(k).normal(size=(n, 3))).to("cuda")
+            api.adjoint(w.system, w.species(), w.gen, n, obs, g)
+            flop = steps * FLOP_PER_STEP + acc * (FLOP_PER_STEP + FLOP_PER_COLUMN_STEP)
+            kname = "k_adj_forward + k_adj_reverse"
+        e1.record(cur)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / 1e3
+        print(f"[bench] {args.workload} pass {k + 1}: {t:.2f} s", file=sys.stderr, flush=True)
+        if k >= args.warmup:
+            times.append(t)
+    secs = sum(times) / len(times)
+    tf = flop / secs / 1e12
+    out = {
+        "metric": "trajectories/s + RK stages/s (FP64, rtol 1e-10): refill kernel vs plain, % FP64 peak",
+        "value": n / secs, "unit": "trajectories/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": secs * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name + ("" if args.workload == "tangent" else "_adjoint"), "trajectories": n,
+                   "what": ("tangent-linear: 12x12 stability matrix + q_x, De columns, FTLE"
+                            if args.workload == "tangent" else
+                            "discrete adjoint of (angle, q, dE) w.r.t. (theta, phi, E, q_x, De), checkpoints "
+                            "every 256 committed steps")},
+        "primal_rk_stages": rhs,
+        "roofline": {"bound": "alu", "kernel": kname, "achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tf / FP64_PEAK_TFLOPS, "traffic": None, "avg_launch_ms": secs * 1e3,
+                     "flop_per_launch": flop},
+    }
+    print(json.dumps(out), flush=True)
 
 
 def chunked_job(api, torch, w, n, args, stats, kernel):
@@ -256,6 +320,12 @@ def main():
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy, 3)
         return
+    if args.workload in ("tangent", "adjoint"):
+        if args.gpus != 1:
+            print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",
+                              "n_gpus": args.gpus}))
+            sys.exit(2)
+        return main_diff(args)
     if args.workload in ("sweep", "stream"):
         if args.gpus != 1:
             print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",
@@ -277,6 +347,10 @@ def main():
     stats = torch.zeros(8, dtype=torch.int64, device="cuda")
     launch = dict(kernel=args.kernel, block=args.block, blocks_per_cu=args.blocks_per_cu,
                   refill_every=args.refill_every)
+    if args.autotune and args.kernel == "persistent":
+        best = api.autotune(w, n=min(w.n, 1 << 16), cache=args.autotune)
+        print(f"[bench] autotuned launch {best}", file=sys.stderr, flush=True)
+        launch.update(block=best["block"], refill_every=best["refill_every"], step_budget=best["step_budget"])
     r = timed_runs(api, torch, w, out, stats, args.steps, args.warmup, **launch)
     K = args.steps
     traj_s = w.n * K / r["total_s"]
