@@ -1,8 +1,7 @@
 """A persistent-kernel pass (counter reset, setup, refill kernel, tail, observables) and the
-histogram reduction captured in a HIP graph: every replay gives the eager result bit for bit.  The graph holds
-kernels and stream-ordered allocations only (counters are cleared by a kernel, not a memset); the
-replays are separated by eager work of the program and synchronisations."""
-import numpy as np
+histogram reduction captured in a HIP graph: every replay gives the eager result bit for bit.  The
+graph holds kernels and stream-ordered allocations only (counters are cleared by a kernel, not a
+memset); the replays are separated by eager work of the program and synchronisations."""
 import pytest
 
 import workloads as W
