@@ -402,6 +402,9 @@ def main():
                         "fp64_frac_peak": FLOP_PER_RHS * rp["rhs"] / rp["total_s"] / (FP64_PEAK_TFLOPS * 1e12),
                         "active_lane_fraction": rp["useful"] / max(rp["issued"], 1), "ms": rp["total_s"] * 1e3}
         res["speedup_vs_plain"] = traj_s / res["plain"]["trajectories_per_s"]
+    pk = api.fp64_peak()
+    res["fp64_peak_measured_tflops"] = pk
+    res["roofline"]["frac_of_measured_peak"] = res["roofline"]["achieved"] / pk
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(res), flush=True)

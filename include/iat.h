@@ -233,6 +233,13 @@ int iat_adjoint(const iat_system* sys, const iat_species* species, int n_species
 int iat_adjoint_workspace_bytes(const iat_system* sys, const iat_species* species, int n_species,
                                 const iat_batch* batch, const iat_obs* obs, size_t* bytes, void* stream);
 
+/* Diagnostics: the FP64 rate this GPU sustains on independent FMAs (eight chains per lane,
+ * n_threads lanes, a multiple of 256, `iters` x 64 FMAs each), timed with HIP events on the
+ * stream; writes TFLOP/s to *tflops (host).  scratch: device double[n_threads] (written).  The
+ * call waits for its kernel.  Not part of the method: the measured denominator next to the
+ * published FP64 vector peak. */
+int iat_fp64_peak(double* scratch, int64_t n_threads, int iters, double* tflops, void* stream);
+
 const char* iat_last_error(void);
 /* Library version string. */
 const char* iat_version(void);

@@ -18,7 +18,7 @@ REDUCE_CELLS, REDUCE_W0_HIST, REDUCE_BOXCOUNT = 1, 2, 3
 W0_BINS, HEAT_BINS = 64, 256
 
 EXPORTS = ["iat_integrate", "iat_integrate_tangent", "iat_adjoint", "iat_reduce", "iat_adjoint_workspace_bytes",
-           "iat_last_error", "iat_version", "iat_release"]
+           "iat_fp64_peak", "iat_last_error", "iat_version", "iat_release"]
 
 _d = ctypes.c_double
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -92,6 +92,8 @@ def load():
     L.iat_adjoint_workspace_bytes.argtypes = [_P(System), _P(Species), ctypes.c_int, _P(Batch), _P(Obs),
                                               _P(ctypes.c_size_t), _vp]
     L.iat_adjoint_workspace_bytes.restype = ctypes.c_int
+    L.iat_fp64_peak.argtypes = [_vp, ctypes.c_int64, ctypes.c_int, _P(ctypes.c_double), _vp]
+    L.iat_fp64_peak.restype = ctypes.c_int
     L.iat_last_error.restype = ctypes.c_char_p
     L.iat_version.restype = ctypes.c_char_p
     L.iat_release.restype = None

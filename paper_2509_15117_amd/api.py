@@ -398,3 +398,12 @@ def autotune(w, *, n: int = 1 << 16, cache: Optional[str] = None, budgets=(5000,
         with open(cache, "w") as f:
             json.dump(data, f, indent=1)
     return best
+
+
+def fp64_peak(n_threads: int = 256 * 2048, iters: int = 20000, stream=None) -> float:
+    """Measured FP64 FMA rate of this GPU in TFLOP/s (see iat_fp64_peak)."""
+    L = _abi.load()
+    scratch = torch.empty(n_threads, dtype=torch.float64, device=torch.device("cuda", torch.cuda.current_device()))
+    out = ctypes.c_double(0.0)
+    _abi.check(L.iat_fp64_peak(_ptr(scratch), n_threads, iters, ctypes.byref(out), _stream_handle(stream)))
+    return out.value

@@ -1,0 +1,58 @@
+"""Qualitative results the paper reports, reproduced by the GPU path (physics smoke tests).
+
+* Fig. 1 text: the regular regions are direct collisions -- one bounce and no complex.
+* Fig. 3 and Fig. 4 (complex formation vs atom and collision energy): on the 225-cell sweep, the
+  probability of complex formation grows with the atom's mass at fixed collision energy and falls
+  with the collision energy for each species.  Checked on 200 trajectories per cell, pooled over
+  q_x and D_e (1800 per species and energy), each comparison allowed 3 standard errors.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2509_15117_amd import api  # noqa: E402
+from paper_2509_15117_amd import _abi  # noqa: E402
+
+
+def test_direct_cells_are_not_complexes():
+    w = W.config1()
+    out = api.integrate_workload(w, counters=False)
+    nb = out["n_bounce"].cpu().numpy()
+    st = out["status"].cpu().numpy()
+    one = nb == 1
+    assert one.any() and (~one).any()
+    assert np.all((st[one] & _abi.ST_COMPLEX) == 0)
+    assert np.all((st[nb >= 2] & _abi.ST_COMPLEX) != 0)
+
+
+def test_complex_probability_trends_on_the_sweep():
+    w = W.config3()
+    w.system.max_steps = 2_000_000       # bound the longest complexes (they are complexes either way)
+    n = 225 * 200
+    print(f"physics: sweep cells, n={n}", flush=True)
+    res = api.run_chunks(w, n=n, chunk=n, n_streams=1, cells=True)
+    c = res["cells"].cpu().numpy().reshape(5, 5, 3, 3, 5)     # species, E, q, De, fields
+    tot = c[..., 0].sum(axis=(2, 3))
+    cpx = c[..., 1].sum(axis=(2, 3))
+    assert np.all(tot == 1800)
+    p = cpx / tot
+    se = np.sqrt(np.maximum(p * (1 - p), 1.0 / tot) / tot)
+    names = w.species_names
+    print("P(complex) species x E (1, 3, 10, 30, 100 uK):\n" + "\n".join(
+        f"  {names[s]:6s} " + " ".join(f"{x:.3f}" for x in p[s]) for s in range(5)), flush=True)
+    masses = np.array([m for m, _ in w.species()])
+    order = np.argsort(masses)
+    for e in range(5):
+        for a, b in zip(order[:-1], order[1:]):            # heavier atom: no fewer complexes
+            assert p[b, e] >= p[a, e] - 3 * np.hypot(se[a, e], se[b, e]), (names[a], names[b], e)
+    for s in range(5):
+        for e in range(4):                                 # higher energy: no more complexes
+            assert p[s, e + 1] <= p[s, e] + 3 * np.hypot(se[s, e], se[s, e + 1]), (names[s], e)
+    # and the trend is real: the heaviest atom at the lowest energy against the lightest at the highest
+    assert p[order[-1], 0] > p[order[0], 4] + 5 * np.hypot(se[order[-1], 0], se[order[0], 4])
