@@ -279,14 +279,12 @@ def cpu_baseline(w, target_s):
 
 
 def sources_digest():
-    """sha256 over the library's HIP sources and headers (names which build the counters were taken on)."""
+    """sha256 over the sources of the integration kernels (names which build the counters were taken on)."""
     import hashlib
     h = hashlib.sha256()
-    for d in (os.path.join(ROOT, "paper_2509_15117_amd", "csrc"), os.path.join(ROOT, "include")):
-        for f in sorted(os.listdir(d)):
-            if f.endswith((".hip", ".h")):
-                h.update(f.encode())
-                h.update(open(os.path.join(d, f), "rb").read())
+    for f in ("iat_device.h", "iat_host.h", "iat_integrate.hip"):
+        h.update(f.encode())
+        h.update(open(os.path.join(ROOT, "paper_2509_15117_amd", "csrc", f), "rb").read())
     return h.hexdigest()
 
 
