@@ -48,6 +48,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--latency", type=int, default=-1, metavar="ID",
+                    help="only time trajectory ID of the workload alone (four-lane tail and one-lane forms) "
+                         "and print the per-step latency")
+    ap.add_argument("--max-steps", type=int, default=0, help="accepted-step cap for --latency (0: the default)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration) and exit")
     return ap.parse_args()
@@ -313,8 +317,33 @@ def calibrate_copy(nbytes, reps):
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "reps": reps}), flush=True)
 
 
+def lone_latency(args):
+    """One trajectory alone on the GPU: the critical path of a batch is its longest trajectory's step
+    count times this per-step latency."""
+    import ctypes
+    import torch
+    from paper_2509_15117_amd import api
+    torch.cuda.set_device(0)
+    w = workload(args.workload)
+    if args.max_steps:
+        w.system.max_steps = args.max_steps
+    api.integrate_workload(w, n=64)          # warm-up
+    res = {"workload": w.name, "id": args.latency}
+    for form, budget in (("four_lane_tail", 1), ("one_lane", -1)):
+        ms = (ctypes.c_float * 4)()
+        o = api.integrate_workload(w, n=1, id0=args.latency, counters=True, kernel="persistent", step_budget=budget,
+                                   kernel_ms=ms)
+        steps = int(o["n_accept"].item() + o["n_reject"].item())
+        t = ms[2] if budget == 1 else ms[1]
+        res[form] = {"attempted_steps": steps, "ms": t, "us_per_step": t * 1e3 / max(steps, 1),
+                     "status": int(o["status"].item())}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     args = parse()
+    if args.latency >= 0:
+        return lone_latency(args)
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy, 3)
         return
