@@ -349,10 +349,11 @@ def run_chunks(w, *, n: Optional[int] = None, chunk: int = 1 << 22, n_streams: i
     return res
 
 
-def autotune(w, *, n: int = 1 << 16, cache: Optional[str] = None, budgets=(5000, 20000, 80000),
+def autotune(w, *, n: int = 1 << 16, cache: Optional[str] = None, budgets=(1, 5000, 20000, 80000),
              blocks=(128, 256), refills=(1, 4, 16), verbose: bool = False) -> Dict[str, int]:
-    """Pick the persistent kernel's launch shape (block size, refill granularity, step budget) for a
-    workload by timing each candidate on its first n ids (HIP events on the current stream), and
+    """Pick the persistent kernel's launch shape (block size, refill granularity, step budget; a budget of
+    1 hands every trajectory to the four-lanes-per-trajectory kernel, 16 per wave, instead of one lane
+    each) for a workload by timing each candidate on its first n ids (HIP events on the current stream), and
     cache the winner in a JSON file keyed by the workload name and n.  Returns keyword arguments for
     integrate() / run_chunks().  Every candidate gives the same bits; only the time differs."""
     import json

@@ -75,3 +75,23 @@ def test_sensitivities_match_central_differences_at_1e_6(gid):
     for k in range(3):
         g, gf = d[k] * s, f[k] * s
         assert np.linalg.norm(g - gf) < 5e-3 * np.linalg.norm(gf)
+
+
+def test_free_particle_limit():
+    """Trap off and no interaction (C4 = 0): the flow is free flight, which every Runge-Kutta step
+    integrates exactly, so the stability matrix at the exit is [[I, tau_f I], [0, I]] in the internal
+    state (positions in a0, velocities per unit of tau = Omega t)."""
+    w = W.config1()
+    w.system.a_x, w.system.q_x = 0.0, 0.0
+    m = w.species()[0][0]
+    p = oracle.base_problem(w.system, (m, 0.0))
+    th, ph = 0.7, 0.3
+    _, Phi, _ = oracle.tangent(p, th, ph, w.system.E, w.system.q_ratio)
+    p["y0"] = oracle.headon_state(th, ph, w.system.E, m, w.system.r0)
+    r = oracle.integrate_one(p)
+    assert r["status"] & oracle.EXITED and r["n_bounce"] == 0
+    tau_f = r["tau_final"]
+    v0 = np.sqrt(2.0 * w.system.E / m) / w.system.omega_rf
+    assert tau_f == pytest.approx(2.0 * w.system.r0 / v0, rel=1e-9)
+    ref = np.block([[np.eye(6), tau_f * np.eye(6)], [np.zeros((6, 6)), np.eye(6)]])
+    assert np.abs(Phi - ref).max() <= 1e-12 * tau_f
