@@ -22,7 +22,10 @@
  * component-major (element k of trajectory j at [k*n + j]), component order
  * r_atom(3), r_ion(3), v_atom(3), v_ion(3).
  * Streams: `stream` is a hipStream_t passed as void*; every call enqueues work on it and
- * returns without synchronising.  NULL means the default stream.
+ * returns without synchronising, except where documented (phase timing through
+ * iat_launch.kernel_ms, sizing of the adjoint workspace, iat_fp64_peak).  NULL means the
+ * default stream.  Calls allocate their scratch stream-ordered (hipMallocAsync/hipFreeAsync)
+ * from the device's default pool, so they can be captured in a HIP graph.
  * Errors: 0 = OK, IAT_EINVAL = bad argument (nothing enqueued), IAT_EHIP = HIP runtime
  * error while enqueueing, IAT_EWORKSPACE = workspace too small, IAT_ENOTSUP = unsupported
  * option.  iat_last_error() returns a thread-local message for the last nonzero return.
@@ -55,7 +58,8 @@ extern "C" {
 #define IAT_ST_MAX_STEPS    (1u << 11) /* accepted-step cap reached                         */
 #define IAT_ST_R_UNDERFLOW  (1u << 12) /* separation below 0.1 r_m (integration broken)     */
 #define IAT_ST_WARN_R0      (1u << 13) /* start violates 10|V(r0)| < E (head-on-run text)   */
-#define IAT_ST_ADJ_SKIPPED  (1u << 14) /* gradient not computed (step cap); grads are NaN   */
+#define IAT_ST_ADJ_SKIPPED  (1u << 14) /* adjoint not computed (no exit or t_max end, or its
+                                          checkpoints did not fit the workspace): NaN       */
 
 #define IAT_MAX_SPECIES 8
 #define IAT_DEFAULT_MAX_STEPS 20000000LL  /* used when iat_system.max_steps == 0 */
@@ -243,7 +247,8 @@ int iat_fp64_peak(double* scratch, int64_t n_threads, int iters, double* tflops,
 const char* iat_last_error(void);
 /* Library version string. */
 const char* iat_version(void);
-/* Free per-device library state (queue counters); safe to call at exit. */
+/* Forget cached device attributes and trim the memory that the library's stream-ordered
+ * allocations left in each device's default pool; safe to call at exit. */
 void iat_release(void);
 
 #ifdef __cplusplus

@@ -510,7 +510,7 @@ __global__ void __launch_bounds__(128) k_adj_post(KParams P, AdjBuf B, double* p
 int64_t reverse_quads(int64_t n)
 {
     int n_cu = 0;
-    if (device_state(&n_cu, nullptr) != 0 || n_cu < 1) n_cu = 256;
+    if (device_state(&n_cu) != 0 || n_cu < 1) n_cu = 256;
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_adj_reverse, 256, 0) != hipSuccess ||
         per_cu < 1)

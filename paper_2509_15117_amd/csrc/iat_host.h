@@ -8,7 +8,7 @@ namespace iat {
 
 int set_error(int code, const char* fmt, ...);
 const char* last_error();
-int device_state(int* n_cu, unsigned long long** queue_slot);
+int device_state(int* n_cu);
 void release_devices();
 int validate_common(const iat_system* sys, const iat_species* species, int n_species, const iat_batch* batch);
 void fill_params(KParams& P, const iat_system* sys, const iat_species* species, int n_species,
