@@ -177,8 +177,9 @@ int iat_integrate(const iat_system* sys, const iat_species* species /* host */, 
                   void* ckpt_ws, size_t ckpt_bytes, void* stream);
 
 /* Reductions of a batch's outputs (the ensemble quantities of Figs. 3 and 4, and the fractal
- * structure of Fig. 1).  obs needs dE_ion, n_bounce and status.  out is device memory; CELLS and W0_HIST
- * ADD to it (zero it first to start), so chunks of one sweep accumulate; BOXCOUNT overwrites it.
+ * structure of Fig. 1).  obs needs dE_ion, n_bounce and status.  out is device memory; CELLS, W0_HIST and
+ * the LIFETIME counts ADD to it (zero it first to start), so chunks of one sweep accumulate;
+ * BOXCOUNT overwrites it.
  * IAT_REDUCE_CELLS (SWEEP batches): per cell c (cell = id mod n_cells), out[5c..5c+4] =
  *   (count, complex count, sum dE_ion, sum dE_ion^2, sum n_bounce); sums run in a fixed order.
  * IAT_REDUCE_W0_HIST: per species slot s of the sweep list (slot 0 otherwise), 64 bins of
@@ -189,10 +190,19 @@ int iat_integrate(const iat_system* sys, const iat_species* species /* host */, 
  *   complex-forming set.  For boxes of s = 2^k cells, N_set(k) = boxes holding a complex cell and
  *   N_bnd(k) = boxes holding both kinds; out[0] = D_boundary, out[1] = D_set (least-squares slopes
  *   of log N against log(1/s) over s = 2..64), out[2+2k] = N_set(k), out[3+2k] = N_bnd(k), k = 0..log2(side);
- *   side 2..32768; NaN slopes when fewer than two levels have boxes. */
+ *   side 2..32768; NaN slopes when fewer than two levels have boxes.
+ * IAT_REDUCE_LIFETIME (the complex survival of Fig. 2; obs also needs t_bounce_first and
+ *   t_bounce_last): per species slot s (as for W0_HIST), out[98*s + b], b < 96: exited complexes
+ *   (>= 2 bounces) by log10((t_last - t_first bounce)/1 us) over [-2, 4] (clamped);
+ *   out[98*s + 96]: complexes still bound at t_max or at the step cap (censored, alive
+ *   throughout); out[98*n_slots + s] = the power-law exponent alpha of the survival fraction,
+ *   S(t) ~ t^-alpha, least squares of log S against log t over bin edges t >= 20 us, from the
+ *   accumulated counts (overwritten by every call; NaN below two points).
+ */
 #define IAT_REDUCE_CELLS 1
 #define IAT_REDUCE_W0_HIST 2
 #define IAT_REDUCE_BOXCOUNT 3
+#define IAT_REDUCE_LIFETIME 4
 int iat_reduce(const iat_system* sys, const iat_species* species, int n_species,
                const iat_batch* batch, const iat_obs* obs, int kind, double* out, void* stream);
 

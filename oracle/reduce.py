@@ -11,6 +11,10 @@ Readings fixed here (the paper draws these quantities but does not give binning 
   one histogram per species slot of the sweep (slot 0 for a grid or explicit arrays).
 * heating histogram: 256 equal bins of sign(dE) log10(1 + |dE| / (k_B x 1 nK)) over
   [-log10(1 + 1e8), +log10(1 + 1e8)], clamped.
+* complex lifetimes (Fig. 2): t_last - t_first bounce of exited complexes, 96 bins of
+  log10(t / 1 us) over [-2, 4] (clamped) per species slot; complexes still bound at t_max or at the
+  step cap are censored (alive throughout); the survival S(t) at each bin's lower edge and its
+  power-law exponent by least squares of log S against log t over edges t >= 20 us.
 * box counting: boxes of s x s cells, s = 2^k; a box is "occupied" when it holds a complex-forming
   cell and on the "boundary" when it holds both kinds; dimensions are least-squares slopes of
   log N(s) against log(1/s) over s = 2 .. 64.
@@ -138,3 +142,43 @@ def boxcount(mask: np.ndarray, kmin: int = 1, kmax: int = 6):
         ys = [math.log(counts[k]) for k in range(kmin, min(kmax, levels - 1) + 1) if counts[k] > 0]
         dims.append(float(np.polyfit(xs, ys, 1)[0]) if len(xs) >= 2 else float("nan"))
     return dims[0], dims[1], n_set, n_bnd
+
+
+AU_TIME_MICRO = 2.4188843265857e-11     # atomic unit of time in microseconds (CODATA 2018)
+LIFE_BINS, LIFE_LO, LIFE_HI = 96, -2.0, 4.0
+EXITED, TMAX, MAX_STEPS = 1 << 2, 1 << 8, 1 << 11
+
+
+def life_coordinate(t_first, t_last):
+    return (np.log10((np.asarray(t_last) - np.asarray(t_first)) * AU_TIME_MICRO) - LIFE_LO) / \
+        (LIFE_HI - LIFE_LO) * LIFE_BINS
+
+
+def lifetime_hist(slot, n_slots, t_first, t_last, n_bounce, status):
+    """(hist (n_slots, 96), censored (n_slots,), coordinate of each finished complex or nan)."""
+    status = np.asarray(status).astype(np.int64)
+    cpx = (status & oracle.COMPLEX) != 0
+    done = cpx & ((status & EXITED) != 0) & (np.asarray(n_bounce) >= 2)
+    cens = cpx & ~done & ((status & (TMAX | MAX_STEPS)) != 0)
+    coord = np.full(len(status), np.nan)
+    coord[done] = life_coordinate(np.asarray(t_first)[done], np.asarray(t_last)[done])
+    hist = np.zeros((n_slots, LIFE_BINS))
+    np.add.at(hist, (np.asarray(slot)[done], _bin(coord[done], LIFE_BINS)), 1.0)
+    censored = np.bincount(np.asarray(slot)[cens], minlength=n_slots).astype(np.float64)
+    return hist, censored, coord
+
+
+def survival(hist, censored):
+    """S at the lower edge of every bin (alive = finished later, or censored)."""
+    total = hist.sum() + censored
+    alive = np.cumsum(hist[::-1])[::-1] + censored
+    return alive / total if total > 0 else np.full(len(hist), np.nan)
+
+
+def survival_exponent(hist, censored, t_min_us=20.0):
+    edges = LIFE_LO + np.arange(LIFE_BINS) * (LIFE_HI - LIFE_LO) / LIFE_BINS
+    S = survival(hist, censored)
+    sel = (edges >= math.log10(t_min_us)) & (S > 0)
+    if sel.sum() < 2:
+        return float("nan")
+    return float(-np.polyfit(edges[sel] * math.log(10.0), np.log(S[sel]), 1)[0])

@@ -14,8 +14,8 @@ ST_R_UNDERFLOW, ST_WARN_R0, ST_ADJ_SKIPPED = 1 << 12, 1 << 13, 1 << 14
 MAX_SPECIES = 8
 GEN_ARRAYS, GEN_GRID, GEN_SWEEP = 0, 1, 2
 KERNEL_PLAIN, KERNEL_PERSISTENT = 1, 2
-REDUCE_CELLS, REDUCE_W0_HIST, REDUCE_BOXCOUNT = 1, 2, 3
-W0_BINS, HEAT_BINS = 64, 256
+REDUCE_CELLS, REDUCE_W0_HIST, REDUCE_BOXCOUNT, REDUCE_LIFETIME = 1, 2, 3, 4
+W0_BINS, HEAT_BINS, LIFE_BINS, LIFE_SLOT = 64, 256, 96, 98
 
 EXPORTS = ["iat_integrate", "iat_integrate_tangent", "iat_adjoint", "iat_reduce", "iat_adjoint_workspace_bytes",
            "iat_fp64_peak", "iat_last_error", "iat_version", "iat_release"]

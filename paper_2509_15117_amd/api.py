@@ -216,6 +216,24 @@ def split_hist(flat: torch.Tensor):
     return flat[: slots * 2 * _abi.W0_BINS].view(slots, _abi.W0_BINS, 2), flat[slots * 2 * _abi.W0_BINS:]
 
 
+def reduce_lifetime(system, species, gen, n, obs, *, id0=None, arrays=None, out=None, stream=None):
+    """Complex lifetimes per species slot (n_slots x 98: 96 log10(t/us) bins over [-2, 4], censored
+    count, spare) followed by the survival power-law exponent per slot; obs needs t_bounce_first/last.
+    Passing the previous out accumulates the counts (the exponents are refitted)."""
+    dev = obs["status"].device
+    slots = len(gen.species) if gen.kind == "sweep" else 1
+    if out is None:
+        out = torch.zeros(slots * _abi.LIFE_SLOT + slots, dtype=torch.float64, device=dev)
+    return _reduce(_abi.REDUCE_LIFETIME, system, species, gen, n, obs, out, id0, arrays, stream)
+
+
+def split_lifetime(flat: torch.Tensor):
+    """(histograms n_slots x 96, censored n_slots, exponents n_slots) views of reduce_lifetime's output."""
+    slots = flat.numel() // (_abi.LIFE_SLOT + 1)
+    h = flat[: slots * _abi.LIFE_SLOT].view(slots, _abi.LIFE_SLOT)
+    return h[:, : _abi.LIFE_BINS], h[:, _abi.LIFE_BINS], flat[slots * _abi.LIFE_SLOT:]
+
+
 def boxcount(system, species, gen, obs, *, stream=None):
     """Box-counting dimensions of the complex-forming set of a whole square power-of-two GRID batch:
     {'D_boundary', 'D_set', 'N_set' (per level k, boxes of 2^k cells), 'N_boundary'}."""

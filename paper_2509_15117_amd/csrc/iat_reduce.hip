@@ -27,7 +27,13 @@ struct RedIn {
     const int32_t* nb;
     const uint32_t* status;
     int64_t n, id0;
+    const double *t_first, *t_last;
 };
+
+// complex lifetimes (t_last - t_first bounce): 96 bins of log10(lifetime / 1 us) over [-2, 4]
+constexpr int kLifeBins = 96, kLifeSlot = kLifeBins + 2;     // + censored count + spare
+constexpr double kLifeLo = -2.0, kLifeHi = 4.0;
+constexpr double kAuTimeMicro = 2.4188843265857e-11;           // atomic unit of time in microseconds
 
 __device__ __forceinline__ int64_t cell_count(const iat_gen& g)
 {
@@ -162,6 +168,64 @@ __global__ void k_box_level(const uint8_t* prev, int side_prev, uint8_t* next, i
     count_box(f, counts, k, live);
 }
 
+// Lifetime histogram per species slot: exited complexes by log10 lifetime; complexes still bound at
+// t_max or at the step cap go to the censored counter (their lifetime is only bounded below).
+__global__ void __launch_bounds__(256) k_reduce_life(KParams P, RedIn R, double* out, int nsp)
+{
+    __shared__ double h[IAT_MAX_SPECIES * kLifeSlot];
+    for (int t = threadIdx.x; t < nsp * kLifeSlot; t += blockDim.x) h[t] = 0.0;
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < R.n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t st = R.status[i];
+        if (!(st & IAT_ST_COMPLEX)) continue;
+        int slot = 0;
+        if (P.gen.kind == IAT_GEN_SWEEP) {
+            TrajParams tp;
+            traj_params(P, i, tp);
+#pragma unroll
+            for (int s = 0; s < IAT_MAX_SPECIES; ++s)
+                slot = (s < P.gen.n_species && P.gen.species[s] == tp.sp) ? s : slot;
+        }
+        if ((st & IAT_ST_EXITED) && R.nb[i] >= 2) {
+            const double x = log10((R.t_last[i] - R.t_first[i]) * kAuTimeMicro);
+            int b = (int)floor((x - kLifeLo) / (kLifeHi - kLifeLo) * kLifeBins);
+            b = b < 0 ? 0 : (b > kLifeBins - 1 ? kLifeBins - 1 : b);
+            atomicAdd(&h[slot * kLifeSlot + b], 1.0);
+        } else if (st & (IAT_ST_TMAX | IAT_ST_MAX_STEPS)) {
+            atomicAdd(&h[slot * kLifeSlot + kLifeBins], 1.0);
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < nsp * kLifeSlot; t += blockDim.x)
+        if (h[t] != 0.0) atomicAdd(&out[t], h[t]);
+}
+
+// Survival S(t) = fraction of complexes alive at the lower edge t of each bin (censored ones alive
+// throughout); power-law exponent = -(LSQ slope of log S against log t) over edges t >= 20 us.
+__global__ void k_life_fit(double* out, int nsp)
+{
+    const int slot = threadIdx.x;
+    if (slot >= nsp) return;
+    const double* h = out + slot * kLifeSlot;
+    double total = h[kLifeBins];
+    for (int b = 0; b < kLifeBins; ++b) total += h[b];
+    double cum = h[kLifeBins], sx = 0, sy = 0, sxx = 0, sxy = 0;
+    int m = 0;
+    const double tmin = log10(20.0);
+    for (int b = kLifeBins - 1; b >= 0; --b) {
+        cum += h[b];
+        const double lt = kLifeLo + b * (kLifeHi - kLifeLo) / kLifeBins;      // log10 of the lower edge
+        if (lt < tmin || total <= 0.0 || cum <= 0.0) continue;
+        const double x = lt * 2.30258509299404568402, y = log(cum / total);
+        sx += x;
+        sy += y;
+        sxx += x * x;
+        sxy += x * y;
+        ++m;
+    }
+    out[nsp * kLifeSlot + slot] = m >= 2 ? -(m * sxy - sx * sy) / (m * sxx - sx * sx) : __builtin_nan("");
+}
+
 __global__ void k_zero_u64(unsigned long long* p, int n)
 {
     for (int t = threadIdx.x; t < n; t += blockDim.x) p[t] = 0ull;
@@ -207,7 +271,8 @@ extern "C" int iat_reduce(const iat_system* sys, const iat_species* species, int
         return set_error(IAT_EINVAL, "reduce: obs.dE_ion, obs.n_bounce and obs.status are required");
     KParams P;
     fill_params(P, sys, species, n_species, batch);
-    RedIn R{obs->dE_ion, obs->n_bounce, obs->status, batch->n, batch->gen.id0};
+    RedIn R{obs->dE_ion, obs->n_bounce, obs->status, batch->n, batch->gen.id0, obs->t_bounce_first,
+            obs->t_bounce_last};
     hipStream_t st = (hipStream_t)stream;
     if (batch->n == 0) return 0;
     if (kind == IAT_REDUCE_CELLS) {
@@ -228,6 +293,13 @@ extern "C" int iat_reduce(const iat_system* sys, const iat_species* species, int
         const int nsp = batch->gen.kind == IAT_GEN_SWEEP ? batch->gen.n_species : 1;
         const int64_t blocks = std::min<int64_t>((batch->n + 255) / 256, 4096);
         hipLaunchKernelGGL(k_reduce_hist, dim3((unsigned)blocks), dim3(256), 0, st, P, R, out, nsp);
+    } else if (kind == IAT_REDUCE_LIFETIME) {
+        if (!obs->t_bounce_first || !obs->t_bounce_last)
+            return set_error(IAT_EINVAL, "reduce LIFETIME needs obs.t_bounce_first and obs.t_bounce_last");
+        const int nsp = batch->gen.kind == IAT_GEN_SWEEP ? batch->gen.n_species : 1;
+        const int64_t blocks = std::min<int64_t>((batch->n + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_reduce_life, dim3((unsigned)blocks), dim3(256), 0, st, P, R, out, nsp);
+        hipLaunchKernelGGL(k_life_fit, dim3(1), dim3(64), 0, st, out, nsp);
     } else if (kind == IAT_REDUCE_BOXCOUNT) {
         const iat_gen& g = batch->gen;
         if (g.kind != IAT_GEN_GRID || g.id0 != 0 || batch->n != (int64_t)g.n_theta * g.n_phi)

@@ -1,6 +1,9 @@
 """Qualitative results the paper reports, reproduced by the GPU path (physics smoke tests).
 
 * Fig. 1 text: the regular regions are direct collisions -- one bounce and no complex.
+* Fig. 2 text: complex lifetimes follow a power law after ~20 us, with an atom-dependent exponent:
+  for every species with enough complexes the survival fraction is a straight line in log-log over
+  20 us .. 1 ms (the residual of the least-squares line below 0.1 in log S).
 * Abstract, Fig. 3 and Fig. 4 text: lower-energy collisions with heavier atoms form complexes more
   often, and complex formation is suppressed above a threshold energy that is greater for heavier
   atoms.  On the 225-cell sweep (200 trajectories per cell, pooled over q_x and D_e: 1800 per
@@ -62,3 +65,29 @@ def test_complex_probability_trends_on_the_sweep():
     assert surv[order[1]] < 0.05 and surv[order[-1]] > 0.5
     # and the trend is strong: the heaviest atom at the lowest energy against the lightest at the highest
     assert p[order[-1], 0] > p[order[0], 4] + 5 * np.hypot(se[order[-1], 0], se[order[0], 4])
+
+
+def test_complex_survival_is_a_power_law():
+    import oracle.reduce as R
+    w = W.fig2_survival()
+    n = 20_000
+    print(f"physics: Fig. 2 survival, n={n}", flush=True)
+    out = api.integrate_workload(w, n=n, counters=True)
+    flat = api.reduce_lifetime(w.system, w.species(), w.gen, n, out)
+    h, cens, expo = (t.cpu().numpy() for t in api.split_lifetime(flat))
+    edges = R.LIFE_LO + np.arange(R.LIFE_BINS) * (R.LIFE_HI - R.LIFE_LO) / R.LIFE_BINS
+    fitted = 0
+    for s, name in enumerate(w.species_names):
+        total = h[s].sum() + cens[s]
+        print(f"  {name:6s} complexes {int(total)} (censored {int(cens[s])}), survival exponent {expo[s]:.3f}",
+              flush=True)
+        if total < 300:
+            continue
+        S = R.survival(h[s], cens[s])
+        sel = (edges >= np.log10(20.0)) & (edges <= 3.0) & (S > 0)
+        x, y = edges[sel] * np.log(10.0), np.log(S[sel])
+        resid = y - np.polyval(np.polyfit(x, y, 1), x)
+        assert np.sqrt(np.mean(resid ** 2)) < 0.1, (name, resid)
+        assert 0.05 < expo[s] < 5.0, (name, expo[s])
+        fitted += 1
+    assert fitted >= 2

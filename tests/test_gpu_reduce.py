@@ -163,3 +163,29 @@ def test_boxcount_of_the_integrated_grid():
     ref_w, ref_h, cw, ch = R.w0_hist(np.arange(w.n), w, dE, st)
     assert np.array_equal(hw, ref_w)          # one energy: a single bin, well inside the axis
     assert _hist_close(hh, ref_h, ch, 256)
+
+
+def test_reduce_lifetime_matches_oracle():
+    """Synthetic lifetimes spanning the axis (and beyond), a sweep generator for the species slots."""
+    w = W.config3()
+    n, id0 = 50_001, 123_456
+    rng = np.random.default_rng(4)
+    t_us = 10.0 ** rng.uniform(-3, 5, n)
+    t_first = rng.uniform(0, 1e12, n)
+    t_last = t_first + t_us / R.AU_TIME_MICRO
+    nb = rng.integers(0, 6, n).astype(np.int32)
+    st = (oracle.COMPLEX * (rng.random(n) < 0.7)) | np.where(rng.random(n) < 0.8, R.EXITED, R.TMAX)
+    st = st.astype(np.int64)
+    obs = {"status": torch.from_numpy(st.astype(np.int32)).to(DEV), "n_bounce": torch.from_numpy(nb).to(DEV),
+           "dE_ion": torch.zeros(n, dtype=torch.float64, device=DEV),
+           "t_bounce_first": torch.from_numpy(t_first).to(DEV), "t_bounce_last": torch.from_numpy(t_last).to(DEV)}
+    print(f"reduce LIFETIME: config3 generator, n={n}, id0={id0}", flush=True)
+    flat = api.reduce_lifetime(w.system, w.species(), w.gen, n, obs, id0=id0)
+    h, cens, expo = (t.cpu().numpy() for t in api.split_lifetime(flat))
+    _, _, slot, _ = R.sweep_params(np.arange(id0, id0 + n), w)
+    ref_h, ref_c, coord = R.lifetime_hist(slot, 5, t_first, t_last, nb, st)
+    assert np.array_equal(cens, ref_c)
+    for s in range(5):
+        assert _hist_close(h[s], ref_h[s], coord[(slot == s) & np.isfinite(coord)], 96), s
+        ref_e = R.survival_exponent(ref_h[s], ref_c[s])
+        assert abs(expo[s] - ref_e) <= 1e-9 * abs(ref_e), (s, expo[s], ref_e)

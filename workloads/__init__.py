@@ -169,4 +169,13 @@ def config5() -> Workload:
                     species_names=["Li6", "K40", "Cs133"], gen=gen)
 
 
+def fig2_survival() -> Workload:
+    """Complex lifetimes (Fig. 2): head-on collisions of the five atoms with Yb+ from random directions
+    and RF phases, E = 1.5 uK, q = 0.2, D_e = 1 K; species = id mod 5."""
+    gen = Generator(kind="sweep", seed=SEED_BASE + 12, species=[0, 1, 2, 3, 4], E_list=[kelvin(1.5e-6)],
+                    q_list=[0.2], De_list=[kelvin(1.0)])
+    return Workload(name="fig2_survival_5species", n=100_000, system=System(), species_names=list(SPECIES_ORDER),
+                    gen=gen)
+
+
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
