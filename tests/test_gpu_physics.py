@@ -103,3 +103,57 @@ def test_complex_survival_is_a_power_law():
         assert 0.05 < expo[s] < 5.0, (name, expo[s])
         fitted += 1
     assert fitted >= 2
+
+
+def _grid(side, q_ratio):
+    w = W.config1()
+    w.gen = W.Generator(kind="grid", n_theta=side, n_phi=side)
+    w.system.q_ratio = q_ratio
+    return w.with_n(side * side)
+
+
+def test_ring_trap_is_azimuthally_symmetric():
+    """Ring trap (q_y = q_x, q_z = -2 q_x): a rotation about z maps trajectories onto each other, so
+    along each theta row of the grid every direct trajectory has the same observables up to the
+    integration's own error: each phi takes its own step sequence, and at rtol 1e-10 the rows agree
+    to ~3e-7 (angle) and ~3e-6 (momentum transfer, relative), tested at 1e-5 (Fig. 1 then shows bands
+    in theta)."""
+    side = 32
+    w = _grid(side, W.RING[1])
+    out = api.integrate_workload(w, counters=False)
+    nb = out["n_bounce"].cpu().numpy().reshape(side, side)
+    ang = out["angle"].cpu().numpy().reshape(side, side)
+    q = out["q_transfer"].cpu().numpy().reshape(side, side)
+    rows, worst = 0, 0.0
+    for j in range(side):
+        if np.all(nb[j] == 1):
+            rows += 1
+            ra, rq = np.ptp(ang[j]) / abs(ang[j]).max(), np.ptp(q[j]) / q[j].max()
+            worst = max(worst, ra, rq)
+            assert ra <= 1e-5 and rq <= 1e-5, (j, ra, rq)
+    print(f"ring trap: {rows} direct theta rows, largest relative spread over phi {worst:.1e}", flush=True)
+    assert rows >= 4
+
+
+def test_linear_trap_saddle_at_pi_over_4():
+    """Linear trap (q_y = -q_x, no RF along z), the configuration of the Fig. 1 discussion: the
+    micromotion at phi = pi/4 is perpendicular to the incoming atom, and the saddle between the two
+    regular regions there is dominated by complexes.  On a 64 x 64 octant grid the four phi columns
+    around pi/4 form complexes more often than the eight columns nearest phi = 0 and pi/2 (measured:
+    the columns peak at 0.81 just below pi/4, against 0.61 near phi = 0 and 0.38 near pi/2)."""
+    side = 64
+    w = _grid(side, W.LINEAR[1])
+    out = api.integrate_workload(w, counters=False)
+    cpx = ((out["status"].cpu().numpy() & _abi.ST_COMPLEX) != 0).reshape(side, side)
+    mid = cpx[:, side // 2 - 2: side // 2 + 2].mean()
+    edge = np.concatenate([cpx[:, :4], cpx[:, -4:]], axis=1).mean()
+    n_mid, n_edge = side * 4, side * 8
+    se = np.sqrt(mid * (1 - mid) / n_mid + edge * (1 - edge) / n_edge)
+    by_col = cpx.mean(axis=0)
+    print("linear trap, P(complex) by phi column:", np.array2string(by_col, precision=2, max_line_width=200),
+          flush=True)
+    assert mid > edge + 3 * se, (mid, edge, se)
+    # and the ring trap has no such structure: its columns agree
+    ring = ((api.integrate_workload(_grid(side, W.RING[1]), counters=False)["status"].cpu().numpy()
+             & _abi.ST_COMPLEX) != 0).reshape(side, side)
+    assert np.ptp(ring.mean(axis=0)) <= 0.1
