@@ -29,7 +29,7 @@ PROBLEM = np.dtype([
     ("m_ion", "f8"), ("m_atom", "f8"), ("C4", "f8"), ("De", "f8"), ("omega", "f8"),
     ("a", "f8", 3), ("q", "f8", 3), ("phase0", "f8"), ("r0", "f8"), ("t_max", "f8"),
     ("rtol", "f8"), ("atol", "f8"), ("h0", "f8"), ("hmax", "f8"), ("hmin", "f8"),
-    ("r_bounce_over_rm", "f8"), ("max_steps", "i8"), ("y0", "f8", 12)])
+    ("r_bounce_over_rm", "f8"), ("max_steps", "i8"), ("y0", "f8", 12), ("exit_centre", "i8")])
 RESULT = np.dtype([
     ("angle", "f8"), ("q_transfer", "f8"), ("dE_ion", "f8"), ("t_dwell", "f8"),
     ("t_first", "f8"), ("t_last", "f8"), ("n_bounce", "i4"), ("status", "u4"),
@@ -75,6 +75,7 @@ def lib():
         L.orc_headon_state.argtypes = [ctypes.c_double] * 5 + [dp]
         L.orc_grid_angles.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_int, dp, dp]
         L.orc_philox4x64_10.argtypes = [vp, vp, vp]
+        L.orc_thermal_normals.argtypes = [ctypes.c_int64, ctypes.c_uint64, dp]
         L.orc_sweep_draw.argtypes = [ctypes.c_int64, ctypes.POINTER(_Sweep), dp, dp, dp, dp, dp, dp,
                                      ctypes.POINTER(ctypes.c_int32)]
         L.orc_observables.argtypes = [vp, dp, dp, ctypes.c_double, dp, dp, dp]
@@ -169,6 +170,36 @@ def sweep_draw(gid: int, gen):
     return dict(cos_theta=ct, phi=ph, phase0=ph0, E=E, q_x=qx, De=De, species=sp.value)
 
 
+K_IN_EH = 3.1668115634556e-6      # k_B x 1 K in hartree (CODATA 2018)
+
+
+def thermal_normals(gid: int, seed: int) -> np.ndarray:
+    z = np.zeros(10)
+    lib().orc_thermal_normals(int(gid), int(seed), _dptr(z))
+    return z[:9]
+
+
+def thermal_state(system, gen, d, m_atom, gid) -> np.ndarray:
+    """Start state (a.u.) of a thermal run (Fig. 3 text): atom on the r0 sphere with Gaussian velocity
+    components at the bath temperature (E = k_B T), turned inward; ion Gaussian at T_ion in the
+    isotropic harmonic trap omega = q_x Omega / 2^(3/2)."""
+    z = thermal_normals(gid, gen.seed)
+    st = math.sqrt(max(0.0, 1.0 - d["cos_theta"] ** 2))
+    n = np.array([st * math.cos(d["phi"]), st * math.sin(d["phi"]), d["cos_theta"]])
+    v = math.sqrt(d["E"] / m_atom) * z[0:3]
+    if v @ n >= 0.0:
+        v = -v
+    omega = d["q_x"] * system.omega_rf / (2.0 * math.sqrt(2.0))
+    kT = gen.T_ion * K_IN_EH
+    sv = math.sqrt(kT / system.m_ion)
+    y = np.zeros(12)
+    y[0:3] = system.r0 * n
+    y[6:9] = v
+    y[3:6] = sv / omega * z[3:6]
+    y[9:12] = sv * z[6:9]
+    return y
+
+
 def problems_for(workload, ids) -> np.ndarray:
     """orc_problem records for global trajectory ids of a workloads.Workload."""
     ids = np.asarray(ids, dtype=np.int64)
@@ -186,6 +217,11 @@ def problems_for(workload, ids) -> np.ndarray:
             p = base_problem(sys_, spec[d["species"]], qx=d["q_x"], De=d["De"], phase0=d["phase0"])
             th = math.acos(d["cos_theta"])
             p["y0"] = headon_state(th, d["phi"], d["E"], p["m_atom"], sys_.r0)
+        elif gen.kind == "thermal":
+            d = sweep_draw(gid, gen)
+            p = base_problem(sys_, spec[d["species"]], qx=d["q_x"], De=d["De"], phase0=d["phase0"])
+            p["y0"] = thermal_state(sys_, gen, d, p["m_atom"], gid)
+            p["exit_centre"] = 1
         else:
             raise ValueError(gen.kind)
         out[i] = p

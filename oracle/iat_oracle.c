@@ -155,6 +155,21 @@ static double radial_rate_sign(const double* y)
     return s;
 }
 
+/* The exit sphere.  Head-on runs start the ion at the trap centre, so the sphere the atom starts
+ * on is the separation r0.  Thermal runs (Fig. 3 caption) start the atom on the sphere of radius
+ * r0 about the trap centre with the ion displaced from it; the separation may then begin above r0
+ * and a grazing atom never cross it from inside, so they stop when the atom leaves that sphere. */
+static double exit_radius(const orc_problem* p, const double* y)
+{
+    if (!p->exit_centre) return separation(y);
+    return sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+}
+static double exit_rate_sign(const orc_problem* p, const double* y)
+{
+    if (!p->exit_centre) return radial_rate_sign(y);
+    return y[0] * y[6] + y[1] * y[7] + y[2] * y[8];
+}
+
 /* relative energy 1/2 mu |v_a - v_i|^2 + V(r), internal units */
 static double relative_energy(const sys_int* S, const double* y)
 {
@@ -202,8 +217,8 @@ void orc_observables(const orc_problem* p, const double y_init[12], const double
  * step from y; the first secant point is the linear interpolation between the step
  * ends.  The last evaluated step is the final state.
  * ------------------------------------------------------------------------- */
-static double exit_locate(const sys_int* S, double tau, const double* y, const double* k1, double h,
-                          double r_prev, double r_new, double r0, double* yf, int64_t* nrhs)
+static double exit_locate(const orc_problem* p, const sys_int* S, double tau, const double* y, const double* k1,
+                          double h, double r_prev, double r_new, double r0, double* yf, int64_t* nrhs)
 {
     double k[7 * NY], ytmp[NY], y5[NY];
     double x0 = 0.0, g0 = r_prev - r0, x1 = h, g1 = r_new - r0;
@@ -214,7 +229,7 @@ static double exit_locate(const sys_int* S, double tau, const double* y, const d
         memcpy(k, k1, sizeof(double) * NY);
         dp5_attempt(NY, traj_rhs, S, tau, y, x2, k, ytmp, y5, NULL);
         *nrhs += 5;
-        double g2 = separation(y5) - r0;
+        double g2 = exit_radius(p, y5) - r0;
         x0 = x1;
         g0 = g1;
         x1 = x2;
@@ -281,7 +296,7 @@ static int integrate_impl(const orc_problem* p, orc_result* R, double* hrec, int
     nrhs = 1;
     double h = h0 < hmax ? h0 : hmax;
     int last_rejected = 0;
-    double r_prev = separation(y), s_prev = radial_rate_sign(y);
+    double r_prev = separation(y), s_prev = radial_rate_sign(y), e_prev = exit_radius(p, y);
 
     for (;;) {
         if (p->max_steps > 0 && n_acc >= p->max_steps) {
@@ -328,8 +343,9 @@ static int integrate_impl(const orc_problem* p, orc_result* R, double* hrec, int
                 if (hrec) { if (n_acc <= cap) hrec[n_acc - 1] = h; else rec_overflow = 1; }
                 break;
             }
-            if (r_prev <= r0 && r_new > r0 && s_new > 0.0) {
-                double hs = exit_locate(&S, tau, y, k, h, r_prev, r_new, r0, yend, &nrhs);
+            double e_new = exit_radius(p, y5);
+            if (e_prev <= r0 && e_new > r0 && exit_rate_sign(p, y5) > 0.0) {
+                double hs = exit_locate(p, &S, tau, y, k, h, e_prev, e_new, r0, yend, &nrhs);
                 /* the located exit step, followed by the full size of that step */
                 if (hrec) { if (n_acc < cap) { hrec[n_acc - 1] = hs; hrec[n_acc] = h; } else rec_overflow = 1; }
                 tau = tau + hs;
@@ -343,6 +359,7 @@ static int integrate_impl(const orc_problem* p, orc_result* R, double* hrec, int
             tau = tau_new;
             r_prev = r_new;
             s_prev = s_new;
+            e_prev = e_new;
             if (final_step) {
                 status |= ORC_TMAX;
                 break;
@@ -486,6 +503,25 @@ void orc_sweep_draw(int64_t id, const orc_sweep* s, double* cos_theta, double* p
     *qx = s->n_q > 0 ? s->q[iq] : s->q_lo + (s->q_hi - s->q_lo) * u[4];
     *De = s->n_De > 0 ? s->De[iD] : s->De_lo * pow(s->De_hi / s->De_lo, u[5]);
     *species = s->species[isp];
+}
+
+/* Box-Muller (G. E. P. Box and M. E. Muller, Ann. Math. Stat. 29, 610 (1958)): from uniforms u in
+ * [0, 1) and v, r = sqrt(-2 ln(1 - u)) gives the normals r cos(2 pi v) and r sin(2 pi v). */
+void orc_thermal_normals(int64_t id, uint64_t seed, double z[10])
+{
+    uint64_t key[2] = {seed, 0};
+    for (int b = 0; b < 3; ++b) {
+        uint64_t c[4] = {(uint64_t)id, (uint64_t)(2 + b), 0, 0}, o[4];
+        orc_philox4x64_10(c, key, o);
+        for (int m = 0; m < 2; ++m) {
+            int j = 2 * (2 * b + m);
+            if (j >= 10) break;
+            double r = sqrt(-2.0 * log(1.0 - u01(o[2 * m])));
+            double a = 2.0 * M_PI * u01(o[2 * m + 1]);
+            z[j] = r * cos(a);
+            z[j + 1] = r * sin(a);
+        }
+    }
 }
 
 /* ---------------------------------------------------------------------------

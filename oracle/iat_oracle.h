@@ -52,6 +52,9 @@ typedef struct {
     double r_bounce_over_rm;     /* periapsis threshold for a bounce, units of r_m  */
     int64_t max_steps;           /* accepted-step cap; 0 = none                     */
     double y0[12];               /* r_atom, r_ion, v_atom, v_ion (a.u.)             */
+    int64_t exit_centre;         /* 0: stop when the atom-ion separation leaves r0
+                                    (head-on runs); 1: when the atom leaves the sphere
+                                    of radius r0 about the trap centre (thermal runs) */
 } orc_problem;
 
 typedef struct {
@@ -87,6 +90,10 @@ typedef struct {
 void orc_sweep_draw(int64_t id, const orc_sweep* s, double* cos_theta, double* phi, double* phase0,
                     double* E, double* qx, double* De, int32_t* species);
 
+/* thermal runs (Fig. 3): nine standard normals z[0..8] of trajectory id by Box-Muller on the
+ * Philox blocks (id, 2..4, 0, 0) under key (seed, 0); z[9] is drawn and unused */
+void orc_thermal_normals(int64_t id, uint64_t seed, double z[10]);
+
 /* observables from an initial and a final state (a.u.) */
 void orc_observables(const orc_problem* p, const double y_init[12], const double y_fin[12],
                      double t_fin, double* angle, double* q_transfer, double* dE_ion);
@@ -105,7 +112,7 @@ double orc_fixed_step_error(int kind, double lam, double t_end, int n_steps);
    Parameter order p = (theta, phi, E, q_x, De); head-on problems only.
    dobs[3*5]: d(angle, q_transfer, dE_ion)/dp;  phi_out[144]: Phi(t_f, 0) with
    rows/cols in the r_atom, r_ion, v_atom, v_ion order (internal units).
-   q_ratio gives dq_k/dq_x per axis.  Returns 0 on success. */
+   q_ratio gives dq_k/dq_x per axis.  Returns 0 on success, -2 for a thermal-run problem. */
 int orc_tangent(const orc_problem* p, double theta, double phi, double E, const double q_ratio[3],
                 double dobs[15], double phi_out[144], double* ftle);
 int orc_fd(const orc_problem* p, double theta, double phi, double E, const double q_ratio[3],

@@ -225,6 +225,7 @@ static void obs_of(const orc_problem* p, const double* vi_au, const double* yf, 
 int orc_tangent(const orc_problem* p0, double theta, double phi, double E, const double q_ratio[3],
                 double dobs[15], double phi_out[144], double* ftle)
 {
+    if (p0->exit_centre) return -2;   /* head-on problems only */
     orc_problem p = *p0;
     double y0[12], dth[12], dph[12], dEy[12];
     headon_internal(&p, theta, phi, E, y0, dth, dph, dEy);
@@ -385,6 +386,7 @@ static int replay_obs(const orc_problem* p, const record* R, double theta, doubl
 int orc_fd(const orc_problem* p0, double theta, double phi, double E, const double q_ratio[3], double rel_h,
            double dobs[15])
 {
+    if (p0->exit_centre) return -2;   /* head-on problems only */
     orc_problem p = *p0;
     double y0[12], dth[12], dph[12], dEy[12];
     headon_internal(&p, theta, phi, E, y0, dth, dph, dEy);

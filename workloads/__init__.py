@@ -95,6 +95,9 @@ class Generator:
     kind = "sweep": counter-based random draws keyed by (seed, id): direction uniform
                     on the sphere, RF phase uniform; E, q, De either from lists (cell
                     digits of id mod the product of list lengths) or from ranges.
+    kind = "thermal": as "sweep" for species, q, De, RF phase and the start point, with E the bath
+                    energy k_B T; atom velocity Gaussian at T (turned inward), ion Gaussian at T_ion
+                    in the isotropic trap omega = q Omega / 2^(3/2) (thermal runs of Fig. 3).
     kind = "arrays": explicit per-trajectory arrays supplied by the caller.
     """
     kind: str = "grid"
@@ -107,6 +110,7 @@ class Generator:
     q_list: List[float] = field(default_factory=list)
     De_list: List[float] = field(default_factory=list)
     E_range: Optional[tuple] = None     # log-uniform
+    T_ion: float = 10e-6                # kind = "thermal": ion temperature (K)
     q_range: Optional[tuple] = None     # uniform
     De_range: Optional[tuple] = None    # log-uniform
 
@@ -175,6 +179,16 @@ def fig2_survival() -> Workload:
     gen = Generator(kind="sweep", seed=SEED_BASE + 12, species=[0, 1, 2, 3, 4], E_list=[kelvin(1.5e-6)],
                     q_list=[0.2], De_list=[kelvin(1.0)])
     return Workload(name="fig2_survival_5species", n=100_000, system=System(), species_names=list(SPECIES_ORDER),
+                    gen=gen)
+
+
+def fig3_thermal() -> Workload:
+    """Thermal runs (Fig. 3): the five atoms with Yb+, bath at 1, 10 and 100 uK, ion at 10 uK,
+    q = 0.2, D_e = 1 and 100 K, uniform RF phase; cell = id mod 30 (species slowest)."""
+    gen = Generator(kind="thermal", seed=SEED_BASE + 13, species=[0, 1, 2, 3, 4],
+                    E_list=[kelvin(x * 1e-6) for x in (1.0, 10.0, 100.0)], q_list=[0.2],
+                    De_list=[kelvin(1.0), kelvin(100.0)], T_ion=10e-6)
+    return Workload(name="fig3_thermal_5species", n=3_000_000, system=System(), species_names=list(SPECIES_ORDER),
                     gen=gen)
 
 
