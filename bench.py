@@ -6,7 +6,7 @@ One "step" = one iat_integrate call over the whole workload (every trajectory in
 its start to its exit or t_max, observables written).  Inputs are generated on the device from
 trajectory ids, so nothing crosses PCIe inside the timed region.
 
-    python bench.py [--steps K] [--warmup W] [--workload grid1024|grid8|sweep]
+    python bench.py [--steps K] [--warmup W] [--workload grid1024|grid8|sweep|stream|thermal|tangent|adjoint]
 """
 from __future__ import annotations
 
@@ -30,7 +30,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="grid1024",
-                    choices=["grid1024", "grid8", "sweep", "stream", "tangent", "adjoint"],
+                    choices=["grid1024", "grid8", "sweep", "stream", "thermal", "tangent", "adjoint"],
                     help="grid1024: the 1024^2 head-on grid (one batch); sweep: the 1.2e7-trajectory 225-cell "
                          "sweep with per-cell reductions; stream: the 1e8-trajectory Li/K/Cs sweep keeping only "
                          "histograms (both in chunks over several streams); tangent / adjoint: the 512^2 "
@@ -60,7 +60,7 @@ def parse():
 def workload(name):
     import workloads as W
     return {"grid1024": W.config2, "grid8": W.config1, "sweep": W.config3, "stream": W.config5,
-            "tangent": W.config4, "adjoint": W.config4}[name]()
+            "thermal": W.fig3_thermal, "tangent": W.config4, "adjoint": W.config4}[name]()
 
 
 # algorithmic FLOP of the differentiation (canonical count): per attempted step of the
@@ -138,7 +138,7 @@ def chunked_job(api, torch, w, n, args, stats, kernel):
               flush=True)
 
     res = api.run_chunks(w, n=n, chunk=chunk, n_streams=args.streams, kernel=kernel,
-                         cells=(w.gen.kind == "sweep" and args.workload == "sweep"),
+                         cells=args.workload in ("sweep", "thermal"),
                          hist=(args.workload == "stream"), stats=stats, progress=progress)
     e1.record(cur)
     torch.cuda.synchronize()
@@ -196,7 +196,8 @@ def main_chunked(args):
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": w.name, "trajectories": n, "chunk": chunk, "streams": args.streams,
                    "kernel": args.kernel, "rtol": w.system.rtol, "atol": w.system.atol,
-                   "reductions": "per-cell sums" if args.workload == "sweep" else "W0 and heating histograms"},
+                   "reductions": ("per-cell sums" if args.workload in ("sweep", "thermal")
+                                  else "W0 and heating histograms")},
         "rk_stages_per_s": stages_s, "accepted_steps_per_s": s[1] / (secs / K),
         "fp64_frac_peak": FLOP_PER_RHS * stages_s / (FP64_PEAK_TFLOPS * 1e12),
         "active_lane_fraction": s[5] / max(s[4], 1),
@@ -205,7 +206,7 @@ def main_chunked(args):
                      "avg_launch_ms": dom["avg_launch_ms"], "flop_per_launch": dom["flop_per_launch"]},
         "kernels": kernels,
     }
-    if args.workload == "sweep" and res is not None:
+    if args.workload in ("sweep", "thermal") and res is not None:
         c = res["cells"].cpu()
         out["p_complex_range"] = [float((c[:, 1] / c[:, 0]).min()), float((c[:, 1] / c[:, 0]).max())]
     if not args.no_plain and args.kernel != "plain":
@@ -353,7 +354,7 @@ def main():
                               "n_gpus": args.gpus}))
             sys.exit(2)
         return main_diff(args)
-    if args.workload in ("sweep", "stream"):
+    if args.workload in ("sweep", "stream", "thermal"):
         if args.gpus != 1:
             print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",
                               "n_gpus": args.gpus}))

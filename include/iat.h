@@ -10,7 +10,8 @@
  * r_m = (C4/(2 De))^(1/4).  Integrated by the adaptive Dormand-Prince 5(4) pair the paper
  * cites.  Head-on start (head-on-run paragraph): ion at rest at the trap centre, atom on the
  * sphere of radius r0 moving radially inward with E = m_a v0^2 / 2.  A trajectory ends when
- * the ion-atom separation crosses r0 outward, or at t_max.
+ * the ion-atom separation crosses r0 outward (thermal runs: when the atom leaves the sphere of
+ * radius r0 about the trap centre), or at t_max.
  *
  * Units: every physical input and output is in atomic units (a0, m_e, E_h, hbar/E_h);
  * angles in radians.  Integration runs internally in length a0 and time tau = Omega t;
@@ -51,7 +52,7 @@ extern "C" {
                                           a direct collision is a single bounce)            */
 #define IAT_ST_BOUND_SEEN   (1u << 1)  /* relative energy < 0 at some accepted step (the
                                           negative-energy bound state of the Eq. (2) text)  */
-#define IAT_ST_EXITED       (1u << 2)  /* separation crossed r0 outward: the normal end     */
+#define IAT_ST_EXITED       (1u << 2)  /* crossed the exit sphere outward: the normal end  */
 #define IAT_ST_TMAX         (1u << 8)  /* reached t_max                                     */
 #define IAT_ST_H_UNDERFLOW  (1u << 9)  /* step size fell below hmin                         */
 #define IAT_ST_NONFINITE    (1u << 10) /* non-finite state                                  */
@@ -90,7 +91,7 @@ typedef struct {
     int64_t max_steps;        /* accepted-step cap; 0 -> IAT_DEFAULT_MAX_STEPS          */
 } iat_system;
 
-enum { IAT_GEN_ARRAYS = 0, IAT_GEN_GRID = 1, IAT_GEN_SWEEP = 2 };
+enum { IAT_GEN_ARRAYS = 0, IAT_GEN_GRID = 1, IAT_GEN_SWEEP = 2, IAT_GEN_THERMAL = 3 };
 
 /* How trajectory ids map to parameters.
  *  GRID : cell-centred (theta, phi) grid on the octant (Fig. 1),
@@ -103,6 +104,16 @@ enum { IAT_GEN_ARRAYS = 0, IAT_GEN_GRID = 1, IAT_GEN_SWEEP = 2 };
  *         De = De_lo (De_hi/De_lo)^u5 or a list.  Lists are indexed by the mixed-radix
  *         digits of cell = id mod (n_species * n_E' * n_q' * n_De') with species slowest
  *         and De fastest (n' = max(n, 1)).
+ *  THERMAL: the thermal runs of Fig. 3.  Species, q_x, De, phase0 and the start point as for
+ *         SWEEP, with E (list or range) the bath energy k_B T.  Blocks (id, 2..4, 0, 0) give
+ *         uniforms w0..w11 and Box-Muller normals z_{2m} = sqrt(-2 ln(1 - w_{2m})) cos(2 pi w_{2m+1}),
+ *         z_{2m+1} = the same with sin.  Atom at r0 n on the sphere, velocity
+ *         sqrt(k_B T / m_a) (z0, z1, z2), negated when it does not point inward (n . v >= 0);
+ *         ion drawn from the thermal distribution at k_B T_ion in the isotropic harmonic trap
+ *         omega = q_x Omega / 2^(3/2): position sqrt(k_B T_ion / (m_i omega^2)) (z3, z4, z5),
+ *         velocity sqrt(k_B T_ion / m_i) (z6, z7, z8).  A thermal trajectory ends when the atom
+ *         crosses the sphere of radius r0 about the trap centre outward (the sphere it started
+ *         on; the separation from the displaced ion may start above r0).  y0 must be NULL.
  *  ARRAYS: per-trajectory device arrays in iat_batch (NULL entries take the defaults). */
 typedef struct {
     int32_t kind;
@@ -115,6 +126,7 @@ typedef struct {
     double E_lo, E_hi, q_lo, q_hi, De_lo, De_hi;
     uint64_t seed;
     int64_t id0;              /* global id of this call's first trajectory (streaming)  */
+    double T_ion;             /* THERMAL: k_B T of the ion's initial distribution (E_h)  */
 } iat_gen;
 
 typedef struct {

@@ -12,7 +12,7 @@ ST_COMPLEX, ST_BOUND_SEEN, ST_EXITED = 1 << 0, 1 << 1, 1 << 2
 ST_TMAX, ST_H_UNDERFLOW, ST_NONFINITE, ST_MAX_STEPS = 1 << 8, 1 << 9, 1 << 10, 1 << 11
 ST_R_UNDERFLOW, ST_WARN_R0, ST_ADJ_SKIPPED = 1 << 12, 1 << 13, 1 << 14
 MAX_SPECIES = 8
-GEN_ARRAYS, GEN_GRID, GEN_SWEEP = 0, 1, 2
+GEN_ARRAYS, GEN_GRID, GEN_SWEEP, GEN_THERMAL = 0, 1, 2, 3
 KERNEL_PLAIN, KERNEL_PERSISTENT = 1, 2
 REDUCE_CELLS, REDUCE_W0_HIST, REDUCE_BOXCOUNT, REDUCE_LIFETIME = 1, 2, 3, 4
 W0_BINS, HEAT_BINS, LIFE_BINS, LIFE_SLOT = 64, 256, 96, 98
@@ -41,7 +41,8 @@ class Gen(ctypes.Structure):
                 ("n_species", ctypes.c_int32), ("species", ctypes.c_int32 * 8), ("n_E", ctypes.c_int32),
                 ("n_q", ctypes.c_int32), ("n_De", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("E", _d * 8), ("q", _d * 8), ("De", _d * 8), ("E_lo", _d), ("E_hi", _d), ("q_lo", _d),
-                ("q_hi", _d), ("De_lo", _d), ("De_hi", _d), ("seed", ctypes.c_uint64), ("id0", ctypes.c_int64)]
+                ("q_hi", _d), ("De_lo", _d), ("De_hi", _d), ("seed", ctypes.c_uint64), ("id0", ctypes.c_int64),
+                ("T_ion", _d)]
 
 
 class Batch(ctypes.Structure):

@@ -10,6 +10,7 @@ import torch
 from . import _abi
 
 KERNELS = {"plain": _abi.KERNEL_PLAIN, "persistent": _abi.KERNEL_PERSISTENT}
+_K_IN_EH = 3.1668115634556e-6        # k_B x 1 K in hartree (CODATA 2018): Generator.T_ion is in kelvin
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -47,7 +48,7 @@ def species_array(species: Sequence) -> "ctypes.Array":
 def gen_struct(g, id0: Optional[int] = None) -> _abi.Gen:
     """From any object with the fields of workloads.Generator."""
     o = _abi.Gen()
-    kinds = {"arrays": _abi.GEN_ARRAYS, "grid": _abi.GEN_GRID, "sweep": _abi.GEN_SWEEP}
+    kinds = {"arrays": _abi.GEN_ARRAYS, "grid": _abi.GEN_GRID, "sweep": _abi.GEN_SWEEP, "thermal": _abi.GEN_THERMAL}
     o.kind = kinds[g.kind]
     o.n_theta, o.n_phi = int(g.n_theta), int(g.n_phi)
     o.n_species = len(g.species)
@@ -68,6 +69,7 @@ def gen_struct(g, id0: Optional[int] = None) -> _abi.Gen:
         o.De_lo, o.De_hi = g.De_range
     o.seed = int(g.seed)
     o.id0 = int(g.id0 if id0 is None else id0)
+    o.T_ion = float(getattr(g, "T_ion", 0.0)) * _K_IN_EH
     return o
 
 
@@ -205,7 +207,7 @@ def reduce_hist(system, species, gen, n, obs, *, id0=None, arrays=None, out=None
     """Complex/total counts over log10(E/W0) per species slot (n_slots x 64 x 2) and the heating histogram
     (256,) in one flat tensor; use split_hist() to view them.  Passing the previous out accumulates."""
     dev = obs["status"].device
-    slots = len(gen.species) if gen.kind == "sweep" else 1
+    slots = len(gen.species) if gen.kind in ("sweep", "thermal") else 1
     if out is None:
         out = torch.zeros(slots * 2 * _abi.W0_BINS + _abi.HEAT_BINS, dtype=torch.float64, device=dev)
     return _reduce(_abi.REDUCE_W0_HIST, system, species, gen, n, obs, out, id0, arrays, stream)
@@ -221,7 +223,7 @@ def reduce_lifetime(system, species, gen, n, obs, *, id0=None, arrays=None, out=
     count, spare) followed by the survival power-law exponent per slot; obs needs t_bounce_first/last.
     Passing the previous out accumulates the counts (the exponents are refitted)."""
     dev = obs["status"].device
-    slots = len(gen.species) if gen.kind == "sweep" else 1
+    slots = len(gen.species) if gen.kind in ("sweep", "thermal") else 1
     if out is None:
         out = torch.zeros(slots * _abi.LIFE_SLOT + slots, dtype=torch.float64, device=dev)
     return _reduce(_abi.REDUCE_LIFETIME, system, species, gen, n, obs, out, id0, arrays, stream)
@@ -329,7 +331,7 @@ def run_chunks(w, *, n: Optional[int] = None, chunk: int = 1 << 22, n_streams: i
     streams = [torch.cuda.Stream(device=dev) for _ in range(max(1, n_streams))]
     m = min(chunk, n)
     bufs = [alloc_obs(m, dev, counters=False) for _ in streams]
-    slots = len(w.gen.species) if w.gen.kind == "sweep" else 1
+    slots = len(w.gen.species) if w.gen.kind in ("sweep", "thermal") else 1
     c_out = [torch.zeros(n_cells(w.gen), 5, dtype=torch.float64, device=dev) for _ in streams] if cells else None
     h_out = ([torch.zeros(slots * 2 * _abi.W0_BINS + _abi.HEAT_BINS, dtype=torch.float64, device=dev)
               for _ in streams] if hist else None)

@@ -559,6 +559,8 @@ static int adj_check(const iat_system* sys, const iat_species* species, int n_sp
     int rc = validate_common(sys, species, n_species, batch);
     if (rc) return rc;
     if (batch->y0) return set_error(IAT_ENOTSUP, "adjoint: only head-on starts (y0 == NULL) have (theta, phi, E)");
+    if (batch->gen.kind == IAT_GEN_THERMAL)
+        return set_error(IAT_ENOTSUP, "adjoint: thermal starts are not parameterised by (theta, phi, E)");
     if (!obs) return set_error(IAT_EINVAL, "obs is NULL");
     if (batch->n > 0 && (!obs->n_accept || !obs->status))
         return set_error(IAT_EINVAL, "adjoint: obs.n_accept and obs.status of the batch's iat_integrate run are required");

@@ -96,7 +96,15 @@ int validate_common(const iat_system* sys, const iat_species* species, int n_spe
         if (g.n_theta < 1 || g.n_phi < 1) return set_error(IAT_EINVAL, "grid n_theta and n_phi must be >= 1");
         if (g.id0 < 0 || g.id0 + batch->n > (int64_t)g.n_theta * g.n_phi)
             return set_error(IAT_EINVAL, "grid ids [id0, id0 + n) exceed n_theta * n_phi");
-    } else if (g.kind == IAT_GEN_SWEEP) {
+    } else if (g.kind == IAT_GEN_SWEEP || g.kind == IAT_GEN_THERMAL) {
+        if (g.kind == IAT_GEN_THERMAL) {
+            if (!(g.T_ion >= 0.0) || !std::isfinite(g.T_ion))
+                return set_error(IAT_EINVAL, "thermal T_ion must be finite and >= 0");
+            if (batch->y0) return set_error(IAT_EINVAL, "thermal batches draw their own start states (y0 must be NULL)");
+            const bool qpos = g.n_q > 0 ? true : g.q_lo > 0.0;
+            for (int k = 0; k < g.n_q; ++k) if (!(g.q[k] > 0.0)) return set_error(IAT_EINVAL, "thermal q_x must be > 0");
+            if (!qpos) return set_error(IAT_EINVAL, "thermal q_x must be > 0 (it sets the ion's trap frequency)");
+        }
         if (g.n_species < 1 || g.n_species > IAT_MAX_SPECIES)
             return set_error(IAT_EINVAL, "sweep n_species must be in [1, %d]", IAT_MAX_SPECIES);
         for (int s = 0; s < g.n_species; ++s)
@@ -123,9 +131,9 @@ int validate_common(const iat_system* sys, const iat_species* species, int n_spe
     } else {
         return set_error(IAT_EINVAL, "unknown generator kind %d", g.kind);
     }
-    if (!batch->E && !finite_pos(sys->E) && !batch->y0 && g.kind != IAT_GEN_SWEEP)
+    if (!batch->E && !finite_pos(sys->E) && !batch->y0 && g.kind != IAT_GEN_SWEEP && g.kind != IAT_GEN_THERMAL)
         return set_error(IAT_EINVAL, "collision energy E must be > 0");
-    if (!batch->De && !finite_pos(sys->De) && !(g.kind == IAT_GEN_SWEEP))
+    if (!batch->De && !finite_pos(sys->De) && !(g.kind == IAT_GEN_SWEEP || g.kind == IAT_GEN_THERMAL))
         return set_error(IAT_EINVAL, "well depth De must be > 0");
     return 0;
 }

@@ -160,7 +160,7 @@ __device__ inline void traj_params(const KParams& P, int64_t i, TrajParams& t)
         const int64_t j = gid / P.gen.n_phi, k = gid % P.gen.n_phi;
         theta = ((double)j + 0.5) * (kTwoPi / 4.0) / (double)P.gen.n_theta;
         phi = ((double)k + 0.5) * (kTwoPi / 4.0) / (double)P.gen.n_phi;
-    } else if (P.gen.kind == IAT_GEN_SWEEP) {
+    } else if (P.gen.kind == IAT_GEN_SWEEP || P.gen.kind == IAT_GEN_THERMAL) {
         uint64_t b0[4] = {(uint64_t)gid, 0, 0, 0}, b1[4] = {(uint64_t)gid, 1, 0, 0};
         philox4x64(b0, P.gen.seed, 0);
         philox4x64(b1, P.gen.seed, 0);
@@ -196,12 +196,57 @@ __device__ inline void traj_params(const KParams& P, int64_t i, TrajParams& t)
     t.cos_p = cos(phi);
 }
 
-// Start state in atomic units: the given y0, else the head-on start.
+// Nine standard normals of a thermal start: Box-Muller on Philox blocks (id, 2..4, 0, 0).
+__device__ inline void thermal_normals(const KParams& P, int64_t gid, double z[10])
+{
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        uint64_t c[4] = {(uint64_t)gid, (uint64_t)(2 + b), 0, 0};
+        philox4x64(c, P.gen.seed, 0);
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            if (2 * (2 * b + m) >= 10) break;
+            const double r = sqrt(-2.0 * log(1.0 - unit_double(c[2 * m])));
+            double sn, cs;
+            sincospi(2.0 * unit_double(c[2 * m + 1]), &sn, &cs);
+            z[2 * (2 * b + m)] = r * cs;
+            z[2 * (2 * b + m) + 1] = r * sn;
+        }
+    }
+}
+
+// Start state in atomic units: the given y0, the thermal start, else the head-on start.
 __device__ inline void start_state_au(const KParams& P, int64_t i, const TrajParams& t, double y[12])
 {
     if (P.y0) {
 #pragma unroll
         for (int k = 0; k < 12; ++k) y[k] = P.y0[(int64_t)k * P.n + i];
+        return;
+    }
+    if (P.gen.kind == IAT_GEN_THERMAL) {
+        double z[10];
+        thermal_normals(P, P.gen.id0 + i, z);
+        const double n0 = t.sin_t * t.cos_p, n1 = t.sin_t * t.sin_p, n2 = t.cos_t;
+        const double sa = sqrt(t.E / species_mass(P, t.sp));
+        double v0 = sa * z[0], v1 = sa * z[1], v2 = sa * z[2];
+        if (v0 * n0 + v1 * n1 + v2 * n2 >= 0.0) {
+            v0 = -v0;
+            v1 = -v1;
+            v2 = -v2;
+        }
+        const double w = t.qx * P.omega / (2.0 * sqrt(2.0));
+        const double sv = sqrt(P.gen.T_ion / P.m_ion), sx = sv / w;
+        y[0] = P.r0 * n0;
+        y[1] = P.r0 * n1;
+        y[2] = P.r0 * n2;
+        y[6] = v0;
+        y[7] = v1;
+        y[8] = v2;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            y[3 + k] = sx * z[3 + k];
+            y[9 + k] = sv * z[6 + k];
+        }
         return;
     }
     const double n0 = t.sin_t * t.cos_p, n1 = t.sin_t * t.sin_p, n2 = t.cos_t;
@@ -516,15 +561,27 @@ __device__ __forceinline__ bool step_prologue(const KParams& P, Scal& S, double&
 enum StepOutcome { OUT_SECANT_CONT = 0, OUT_SECANT_DONE, OUT_REJECT, OUT_NONFINITE, OUT_ACCEPT, OUT_STOP_RFLOOR,
                    OUT_ENTER_EXIT, OUT_TMAX };
 
-// Bookkeeping after a step, shared by both forms.  g: separation minus r0 of the new state
-// (secant mode) ; rho_new, s_new, w2: geometry of the new state (normal mode); fin: final step.
+// Where a trajectory leaves.  Head-on runs stop when the atom-ion separation crosses r0 outward
+// (the ion starts at the centre, so that sphere is the start sphere).  Thermal runs (Fig. 3)
+// displace the ion from the centre, so the separation can start above r0 and a grazing atom would
+// never cross it from inside; they stop when the atom leaves the sphere of radius r0 about the
+// trap centre on which it started.  The choice is a compile-time parameter (CE = centre exit) so
+// the head-on kernels carry none of it.
+// Exit geometry of CE runs: e = |r_atom|^2 and its rate sign r_atom . v_atom.
+
+// Bookkeeping after a step, shared by both forms.  rho_new, s_new, w2: separation^2, its rate sign
+// and the relative speed^2 of the new state; e_prev, e_new, se_new: the exit geometry of the step
+// start and of the new state when CE (else the separation is the exit geometry); fin: final step.
+// In secant mode only the exit radius of the new state is used.
+template <bool CE = false>
 __device__ __forceinline__ StepOutcome step_epilogue(const KParams& P, Scal& S, const Lane& L, double h, bool fin,
                                                      double en, bool finite, double rho_new, double s_new,
-                                                     double w2)
+                                                     double w2, double e_prev = 0.0, double e_new = 0.0,
+                                                     double se_new = 0.0)
 {
     if (S.mode != 0) {
         S.nrhs += 5;
-        const double g2 = sqrt(rho_new) - P.r0;
+        const double g2 = sqrt(CE ? e_new : rho_new) - P.r0;
         S.rho_prev = S.sx1;
         S.s_prev = S.sg1;
         S.sx1 = h;
@@ -564,13 +621,14 @@ __device__ __forceinline__ StepOutcome step_epilogue(const KParams& P, Scal& S, 
         S.done = 1;
         return OUT_STOP_RFLOOR;
     }
-    if (S.rho_prev <= P.r0sq && rho_new > P.r0sq && s_new > 0.0) {
+    const double ex_prev = CE ? e_prev : S.rho_prev, ex_new = CE ? e_new : rho_new;
+    if (ex_prev <= P.r0sq && ex_new > P.r0sq && (CE ? se_new : s_new) > 0.0) {
         // keep y_n; the next four steps are secant iterates, (x0, g0) kept in (rho_prev, s_prev)
         S.mode = 1;
-        S.s_prev = sqrt(S.rho_prev) - P.r0;
+        S.s_prev = sqrt(ex_prev) - P.r0;
         S.rho_prev = 0.0;
         S.sx1 = h;
-        S.sg1 = sqrt(rho_new) - P.r0;
+        S.sg1 = sqrt(ex_new) - P.r0;
         S.h = h;
         return OUT_ENTER_EXIT;
     }
@@ -713,6 +771,7 @@ __device__ __forceinline__ void traj1_store(const Work& W, int64_t i, const Traj
 }
 
 // One attempted step (or secant iterate) of a one-lane trajectory.
+template <bool CE = false>
 __device__ __forceinline__ void traj1_advance(const KParams& P, Traj1& T)
 {
     double h;
@@ -766,7 +825,13 @@ __device__ __forceinline__ void traj1_advance(const KParams& P, Traj1& T)
     const double rho_new = dot3(d0, d1, d2, d0, d1, d2);
     const double s_new = dot3(d0, d1, d2, w0, w1, w2);
     const double ww = dot3(w0, w1, w2, w0, w1, w2);
-    const StepOutcome o = step_epilogue(P, T.S, T.L, h, fin, en, finite, rho_new, s_new, ww);
+    double e_prev = 0.0, e_new = 0.0, se_new = 0.0;
+    if (CE) {
+        e_prev = dot3(T.x[0], T.x[1], T.x[2], T.x[0], T.x[1], T.x[2]);
+        e_new = dot3(x5[0], x5[1], x5[2], x5[0], x5[1], x5[2]);
+        se_new = dot3(x5[0], x5[1], x5[2], v5[0], v5[1], v5[2]);
+    }
+    const StepOutcome o = step_epilogue<CE>(P, T.S, T.L, h, fin, en, finite, rho_new, s_new, ww, e_prev, e_new, se_new);
     if (o == OUT_SECANT_DONE || o == OUT_STOP_RFLOOR) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
@@ -891,6 +956,7 @@ __device__ inline void traj4_start(const KParams& P, const Work& W, int64_t i, T
 
 // One attempted step of the four-lane form.  Returns the StepOutcome, or -1 when the trajectory
 // stopped before stepping (step cap, step underflow); h_used receives the step size tried.
+template <bool CE = false>
 __device__ __forceinline__ int traj4_step(const KParams& P, Traj4& T, double& h_used)
 {
     double h;
@@ -936,7 +1002,16 @@ __device__ __forceinline__ int traj4_step(const KParams& P, Traj4& T, double& h_
     const double rho_new = dot3(d0, d1, d2, d0, d1, d2);
     const double s_new = dot3(d0, d1, d2, w0, w1, w2);
     const double ww = dot3(w0, w1, w2, w0, w1, w2);
-    const StepOutcome o = step_epilogue(P, T.S, T.L, h, fin, en, finite, rho_new, s_new, ww);
+    double e_prev = 0.0, e_new = 0.0, se_new = 0.0;
+    if (CE) {
+        const double p0 = quad_bcast<0>(T.xa), p1 = quad_bcast<1>(T.xa), p2 = quad_bcast<2>(T.xa);
+        const double a0 = quad_bcast<0>(x5a), a1 = quad_bcast<1>(x5a), a2 = quad_bcast<2>(x5a);
+        const double u0 = quad_bcast<0>(v5a), u1 = quad_bcast<1>(v5a), u2 = quad_bcast<2>(v5a);
+        e_prev = dot3(p0, p1, p2, p0, p1, p2);
+        e_new = dot3(a0, a1, a2, a0, a1, a2);
+        se_new = dot3(a0, a1, a2, u0, u1, u2);
+    }
+    const StepOutcome o = step_epilogue<CE>(P, T.S, T.L, h, fin, en, finite, rho_new, s_new, ww, e_prev, e_new, se_new);
     if (o == OUT_SECANT_DONE || o == OUT_STOP_RFLOOR) {
         T.xa = x5a;
         T.xi = x5i;
@@ -953,10 +1028,11 @@ __device__ __forceinline__ int traj4_step(const KParams& P, Traj4& T, double& h_
     return (int)o;
 }
 
+template <bool CE = false>
 __device__ __forceinline__ void traj4_advance(const KParams& P, Traj4& T)
 {
     double h;
-    (void)traj4_step(P, T, h);
+    (void)traj4_step<CE>(P, T, h);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -71,6 +71,7 @@ __global__ void __launch_bounds__(256) k_observe(KParams P, Work W)
     if (i < P.n) work_observe(P, W, i);
 }
 
+template <bool CE>
 __global__ void __launch_bounds__(256) k_integrate_plain(KParams P, Work W)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -80,7 +81,7 @@ __global__ void __launch_bounds__(256) k_integrate_plain(KParams P, Work W)
         Traj1 T;
         traj1_start(P, W, i, T);
         while (!T.S.done) {
-            traj1_advance(P, T);
+            traj1_advance<CE>(P, T);
             ++iters;
         }
         traj1_store(W, i, T);
@@ -97,6 +98,7 @@ __global__ void __launch_bounds__(256) k_integrate_plain(KParams P, Work W)
 // Persistent refill kernel.  A trajectory that has used `budget` attempted steps without
 // finishing is suspended into the continuation records (while slots last) and its lane takes
 // new work; k_integrate_tail finishes the suspended ones four lanes per trajectory.
+template <bool CE>
 __global__ void __launch_bounds__(256) k_integrate_persistent(KParams P, Work W, unsigned long long* queue, Cont C)
 {
     const int lane = __lane_id();
@@ -123,7 +125,7 @@ __global__ void __launch_bounds__(256) k_integrate_persistent(KParams P, Work W,
         }
         if (!__any(active)) break;
         for (int k = 0; k < P.refill_every; ++k) {
-            if (active && !T.S.done) traj1_advance(P, T);
+            if (active && !T.S.done) traj1_advance<CE>(P, T);
         }
         iters += P.refill_every;
         if (active) {
@@ -154,6 +156,7 @@ __global__ void __launch_bounds__(256) k_integrate_persistent(KParams P, Work W,
 
 // Finishes suspended trajectories with four lanes each (one per axis): the per-step latency of
 // a long-lived complex is what bounds a batch's wall time.
+template <bool CE>
 __global__ void __launch_bounds__(256) k_integrate_tail(KParams P, Work W, Cont C)
 {
     const int lane = __lane_id();
@@ -189,7 +192,7 @@ __global__ void __launch_bounds__(256) k_integrate_tail(KParams P, Work W, Cont 
             }
         }
         if (!__any(active)) break;
-        if (active && !T.S.done) traj4_advance(P, T);
+        if (active && !T.S.done) traj4_advance<CE>(P, T);
         ++iters;
         if (active && T.S.done) {
             traj4_store(W, i, T, lane & 3);
@@ -296,29 +299,35 @@ extern "C" int iat_integrate(const iat_system* sys, const iat_species* species, 
     timer.mark(0);
     hipLaunchKernelGGL(k_setup, dim3(nblk), dim3(256), 0, st, P, W);
     timer.mark(1);
+    // thermal runs leave through the start sphere about the trap centre (CE kernels)
+    const bool ce = batch->gen.kind == IAT_GEN_THERMAL;
+    const void* k_plain = ce ? (const void*)k_integrate_plain<true> : (const void*)k_integrate_plain<false>;
+    const void* k_pers = ce ? (const void*)k_integrate_persistent<true> : (const void*)k_integrate_persistent<false>;
+    const void* k_tail = ce ? (const void*)k_integrate_tail<true> : (const void*)k_integrate_tail<false>;
     if (L.kernel == IAT_KERNEL_PLAIN) {
-        hipLaunchKernelGGL(k_integrate_plain, dim3((unsigned)((n + L.block - 1) / L.block)), dim3(L.block), 0, st, P, W);
+        void* args[] = {&P, &W};
+        (void)hipLaunchKernel(k_plain, dim3((unsigned)((n + L.block - 1) / L.block)), dim3(L.block), args, 0, st);
     } else {
         int per_cu = L.blocks_per_cu;
         if (per_cu == 0) {
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_integrate_persistent, L.block,
-                                                             0) != hipSuccess || per_cu < 1)
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pers, L.block, 0) != hipSuccess || per_cu < 1)
                 per_cu = 1;
         }
         int64_t blocks = (int64_t)n_cu * per_cu;
         const int64_t need = (n + L.block - 1) / L.block;
         if (blocks > need) blocks = need;
-        hipLaunchKernelGGL(k_integrate_persistent, dim3((unsigned)blocks), dim3(L.block), 0, st, P, W, q, C);
+        void* args[] = {&P, &W, &q, &C};
+        (void)hipLaunchKernel(k_pers, dim3((unsigned)blocks), dim3(L.block), args, 0, st);
         timer.mark(2);
         if (cap > 0) {
             int per_cu4 = 1;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu4, (const void*)k_integrate_tail, 256, 0) !=
-                    hipSuccess || per_cu4 < 1)
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu4, k_tail, 256, 0) != hipSuccess || per_cu4 < 1)
                 per_cu4 = 1;
             int64_t blocks4 = (int64_t)n_cu * per_cu4;
             const int64_t need4 = (4 * cap + 255) / 256;
             if (blocks4 > need4) blocks4 = need4;
-            hipLaunchKernelGGL(k_integrate_tail, dim3((unsigned)blocks4), dim3(256), 0, st, P, W, C);
+            void* args4[] = {&P, &W, &C};
+            (void)hipLaunchKernel(k_tail, dim3((unsigned)blocks4), dim3(256), args4, 0, st);
         }
     }
     if (L.kernel == IAT_KERNEL_PLAIN) timer.mark(2);

@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(256) k_reduce_hist(KParams P, RedIn R, double*
 #pragma unroll
         for (int s = 0; s < IAT_MAX_SPECIES; ++s)
             slot = (s < P.gen.n_species && P.gen.species[s] == tp.sp) ? s : slot;
-        if (P.gen.kind != IAT_GEN_SWEEP) slot = 0;
+        if (P.gen.kind != IAT_GEN_SWEEP && P.gen.kind != IAT_GEN_THERMAL) slot = 0;
         atomicAdd(&hw[(slot * 64 + b) * 2 + 0], 1.0);
         if (R.status[i] & IAT_ST_COMPLEX) atomicAdd(&hw[(slot * 64 + b) * 2 + 1], 1.0);
         const double e = R.dE[i];
@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(256) k_reduce_life(KParams P, RedIn R, double*
         const uint32_t st = R.status[i];
         if (!(st & IAT_ST_COMPLEX)) continue;
         int slot = 0;
-        if (P.gen.kind == IAT_GEN_SWEEP) {
+        if (P.gen.kind == IAT_GEN_SWEEP || P.gen.kind == IAT_GEN_THERMAL) {
             TrajParams tp;
             traj_params(P, i, tp);
 #pragma unroll
@@ -276,7 +276,8 @@ extern "C" int iat_reduce(const iat_system* sys, const iat_species* species, int
     hipStream_t st = (hipStream_t)stream;
     if (batch->n == 0) return 0;
     if (kind == IAT_REDUCE_CELLS) {
-        if (batch->gen.kind != IAT_GEN_SWEEP) return set_error(IAT_EINVAL, "reduce CELLS needs a SWEEP batch");
+        if (batch->gen.kind != IAT_GEN_SWEEP && batch->gen.kind != IAT_GEN_THERMAL)
+            return set_error(IAT_EINVAL, "reduce CELLS needs a SWEEP or THERMAL batch");
         const iat_gen& g = batch->gen;
         const int64_t ncell = (int64_t)g.n_species * (g.n_E > 0 ? g.n_E : 1) * (g.n_q > 0 ? g.n_q : 1) *
                               (g.n_De > 0 ? g.n_De : 1);
@@ -290,13 +291,13 @@ extern "C" int iat_reduce(const iat_system* sys, const iat_species* species, int
                            (const double*)part, ncell, out);
         if (hipFreeAsync(part, st) != hipSuccess) return set_error(IAT_EHIP, "hipFreeAsync failed");
     } else if (kind == IAT_REDUCE_W0_HIST) {
-        const int nsp = batch->gen.kind == IAT_GEN_SWEEP ? batch->gen.n_species : 1;
+        const int nsp = (batch->gen.kind == IAT_GEN_SWEEP || batch->gen.kind == IAT_GEN_THERMAL) ? batch->gen.n_species : 1;
         const int64_t blocks = std::min<int64_t>((batch->n + 255) / 256, 4096);
         hipLaunchKernelGGL(k_reduce_hist, dim3((unsigned)blocks), dim3(256), 0, st, P, R, out, nsp);
     } else if (kind == IAT_REDUCE_LIFETIME) {
         if (!obs->t_bounce_first || !obs->t_bounce_last)
             return set_error(IAT_EINVAL, "reduce LIFETIME needs obs.t_bounce_first and obs.t_bounce_last");
-        const int nsp = batch->gen.kind == IAT_GEN_SWEEP ? batch->gen.n_species : 1;
+        const int nsp = (batch->gen.kind == IAT_GEN_SWEEP || batch->gen.kind == IAT_GEN_THERMAL) ? batch->gen.n_species : 1;
         const int64_t blocks = std::min<int64_t>((batch->n + 255) / 256, 4096);
         hipLaunchKernelGGL(k_reduce_life, dim3((unsigned)blocks), dim3(256), 0, st, P, R, out, nsp);
         hipLaunchKernelGGL(k_life_fit, dim3(1), dim3(64), 0, st, out, nsp);

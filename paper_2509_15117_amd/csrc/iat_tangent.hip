@@ -452,6 +452,8 @@ extern "C" int iat_integrate_tangent(const iat_system* sys, const iat_species* s
     int rc = validate_common(sys, species, n_species, batch);
     if (rc) return rc;
     if (batch->y0) return set_error(IAT_ENOTSUP, "tangent: only head-on starts (y0 == NULL) have (theta, phi, E)");
+    if (batch->gen.kind == IAT_GEN_THERMAL)
+        return set_error(IAT_ENOTSUP, "tangent: thermal starts are not parameterised by (theta, phi, E)");
     if (!obs) return set_error(IAT_EINVAL, "obs is NULL");
     if (batch->n > 0 &&
         (!obs->angle || !obs->q_transfer || !obs->dE_ion || !obs->t_dwell || !obs->n_bounce || !obs->status || !dobs_dp))

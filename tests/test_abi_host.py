@@ -30,7 +30,7 @@ def test_library_exports_every_declared_function():
 def test_struct_layouts_match_header_sizes():
     # sizes implied by the header's field lists (LP64)
     assert ctypes.sizeof(_abi.System) == 8 * 21 + 8 + 8
-    assert ctypes.sizeof(_abi.Gen) == 64 + 8 * 30 + 16
+    assert ctypes.sizeof(_abi.Gen) == 64 + 8 * 30 + 16 + 8
     assert ctypes.sizeof(_abi.Obs) == 12 * 8
     assert ctypes.sizeof(_abi.Launch) == 32 + 8
 

@@ -67,10 +67,44 @@ def test_sweep_parity_ragged(kernel):
     assert_parity(P, ref, got, f"sweep/{kernel}", min_direct=400)
 
 
+def test_thermal_start_states_match_the_oracle():
+    """Thermal-run starts (Fig. 3): after a 1 ns run (two steps) the GPU state equals the oracle's
+    to the last bits -- the Philox blocks, the Box-Muller normals and the state built from them."""
+    w = W.fig3_thermal()
+    w.system.t_max = W.seconds(1e-9)
+    id0, n = 987_654, 1000
+    got = run(w, n=n, id0=id0)
+    P, ref = oracle_run(w, np.arange(id0, id0 + n))
+    assert np.all(got["status"] & oracle.TMAX) and np.all(ref["status"] & oracle.TMAX)
+    assert np.array_equal(got["n_accept"], ref["n_accept"])
+    yr = np.stack(ref["y_final"], axis=1)
+    scale = np.abs(yr).max(axis=1, keepdims=True)
+    err = np.abs(got["y_final"] - yr) / scale
+    print(f"thermal starts: n={n}, max |gpu - oracle| / component scale {err.max():.1e}", flush=True)
+    assert err.max() < 1e-13
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_thermal_parity_ragged(kernel):
+    """1000 thermal-run ids (ragged, id0 offset): direct trajectories one by one, the rest in
+    ensemble; the exit is the sphere about the trap centre."""
+    w = W.fig3_thermal()
+    w.system.max_steps = 2_000_000
+    id0 = 31_337
+    got = run(w, n=1000, id0=id0, kernel=kernel)
+    P, ref = oracle_run(w, np.arange(id0, id0 + 1000))
+    r_atom = np.linalg.norm(got["y_final"][0:3], axis=0)
+    ex = (got["status"].astype(np.int64) & oracle.EXITED) != 0
+    assert np.all(np.abs(r_atom[ex] - w.system.r0) < 1e-8 * w.system.r0)
+    assert_parity(P, ref, got, f"thermal/{kernel}", min_direct=400)
+
+
 def test_plain_and_persistent_are_bitwise_identical():
     """Same ids -> same bits, whichever kernel, lane or launch shape; a small step budget sends
     most trajectories through the four-lanes-per-trajectory kernel, so it is checked too."""
-    for w, n in ((W.config1(), 64), (W.config3(), 3001)):
+    thermal = W.fig3_thermal()
+    thermal.system.max_steps = 2_000_000
+    for w, n in ((W.config1(), 64), (W.config3(), 3001), (thermal, 2001)):
         a = run(w, n=n, kernel="plain")
         for kw in (dict(block=256), dict(block=64, refill_every=4), dict(block=128, blocks_per_cu=1),
                    dict(step_budget=-1), dict(step_budget=7), dict(step_budget=500, refill_every=3)):
