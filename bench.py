@@ -6,7 +6,7 @@ One "step" = one iat_integrate call over the whole workload (every trajectory in
 its start to its exit or t_max, observables written).  Inputs are generated on the device from
 trajectory ids, so nothing crosses PCIe inside the timed region.
 
-    python bench.py [--steps K] [--warmup W] [--workload grid1024|grid8|sweep|stream|thermal|tangent|adjoint]
+    python bench.py [--steps K] [--warmup W] [--workload grid1024|grid8|sweep|stream|thermal|fig4|tangent|adjoint]
 """
 from __future__ import annotations
 
@@ -30,7 +30,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="grid1024",
-                    choices=["grid1024", "grid8", "sweep", "stream", "thermal", "tangent", "adjoint"],
+                    choices=["grid1024", "grid8", "sweep", "stream", "thermal", "fig4", "tangent", "adjoint"],
                     help="grid1024: the 1024^2 head-on grid (one batch); sweep: the 1.2e7-trajectory 225-cell "
                          "sweep with per-cell reductions; stream: the 1e8-trajectory Li/K/Cs sweep keeping only "
                          "histograms (both in chunks over several streams); tangent / adjoint: the 512^2 "
@@ -60,7 +60,7 @@ def parse():
 def workload(name):
     import workloads as W
     return {"grid1024": W.config2, "grid8": W.config1, "sweep": W.config3, "stream": W.config5,
-            "thermal": W.fig3_thermal, "tangent": W.config4, "adjoint": W.config4}[name]()
+            "thermal": W.fig3_thermal, "fig4": W.fig4_energy, "tangent": W.config4, "adjoint": W.config4}[name]()
 
 
 # algorithmic FLOP of the differentiation (canonical count): per attempted step of the
@@ -139,7 +139,7 @@ def chunked_job(api, torch, w, n, args, stats, kernel):
 
     res = api.run_chunks(w, n=n, chunk=chunk, n_streams=args.streams, kernel=kernel,
                          cells=args.workload in ("sweep", "thermal"),
-                         hist=(args.workload == "stream"), stats=stats, progress=progress)
+                         hist=args.workload in ("stream", "fig4"), stats=stats, progress=progress)
     e1.record(cur)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / 1e3, res, chunk
@@ -354,7 +354,7 @@ def main():
                               "n_gpus": args.gpus}))
             sys.exit(2)
         return main_diff(args)
-    if args.workload in ("sweep", "stream", "thermal"):
+    if args.workload in ("sweep", "stream", "thermal", "fig4"):
         if args.gpus != 1:
             print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",
                               "n_gpus": args.gpus}))

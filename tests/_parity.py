@@ -93,9 +93,12 @@ def _direct(res, i):
     return res[i]["n_bounce"] <= 1 and (res[i]["status"] & oracle.EXITED) != 0
 
 
-def probe_spread(problems, ref, idx):
+def probe_spread(problems, ref, idx, step_rates=None):
     """Round-off spread s of each trajectory in idx: the worst field difference between the
-    oracle and five round-off probes of it.  inf when a probe is no longer a direct exit."""
+    oracle and five round-off probes of it.  inf when a probe is no longer a direct exit.
+    step_rates (a list), if given, receives for each probe the fraction of idx whose accepted or
+    rejected step count differs from the oracle's: how often round-off alone changes the step
+    sequence on this workload."""
     idx = np.asarray(idx, dtype=np.int64)
     if len(idx) == 0:
         return np.zeros(0)
@@ -107,6 +110,9 @@ def probe_spread(problems, ref, idx):
         runs.append(oracle.integrate(q))
     spread = np.zeros(len(idx))
     for run in runs:
+        if step_rates is not None:
+            step_rates.append(float(np.mean((run["n_accept"] != ref["n_accept"][idx]) |
+                                            (run["n_reject"] != ref["n_reject"][idx]))))
         g = as_outputs(run)
         for j, i in enumerate(idx):
             if not _direct(run, j):
@@ -116,15 +122,15 @@ def probe_spread(problems, ref, idx):
     return spread
 
 
-def classify(problems, ref, got):
+def classify(problems, ref, got, step_rates=None):
     """Split trajectory indices into direct ones (<= 1 bounce and a normal exit in the oracle, in
     every round-off probe and in the library), with their round-off spread s, and the rest
-    (compared in ensemble).  Returns (direct, spread, rest)."""
+    (compared in ensemble).  Returns (direct, spread, rest); step_rates as in probe_spread."""
     gs = got["status"].astype(np.int64)
     one = (ref["n_bounce"] <= 1) & ((ref["status"] & oracle.EXITED) != 0) & (got["n_bounce"] <= 1) & \
           ((gs & oracle.EXITED) != 0)
     cand = np.where(one)[0]
-    spread = probe_spread(problems, ref, cand)
+    spread = probe_spread(problems, ref, cand, step_rates)
     ok = np.isfinite(spread)
     rest = np.sort(np.concatenate([np.where(~one)[0], cand[~ok]]))
     return cand[ok], spread[ok], rest

@@ -32,7 +32,8 @@ def oracle_run(w, ids):
 
 
 def assert_parity(P, ref, got, name, min_direct=1):
-    direct, spread, rest = PT.classify(P, ref, got)
+    rates = []
+    direct, spread, rest = PT.classify(P, ref, got, step_rates=rates)
     n_strict = int(np.sum(spread <= 0.1 * PT.REL))
     print(f"{name}: {len(direct)} direct ({n_strict} with round-off spread <= 1e-9, bar 1e-8), "
           f"{len(rest)} in ensemble", flush=True)
@@ -41,7 +42,11 @@ def assert_parity(P, ref, got, name, min_direct=1):
     assert not bad, f"{name}: per-trajectory mismatches {bad[:10]} (of {len(direct)})"
     same = np.mean([got["n_accept"][i] == ref["n_accept"][i] and got["n_reject"][i] == ref["n_reject"][i]
                     for i in direct]) if len(direct) else 1.0
-    assert same >= 0.99, f"{name}: step counts differ on {1 - same:.1%} of direct trajectories"
+    # step counts: identical on >= 99 %, or, where round-off alone changes the oracle's own step
+    # sequence more often (its five probes), on all but twice the probes' worst rate
+    allowed = max(0.01, 2.0 * max(rates, default=0.0))
+    assert 1 - same <= allowed, (f"{name}: step counts differ on {1 - same:.1%} of direct trajectories "
+                                 f"(the oracle's round-off probes: {[f'{r:.1%}' for r in rates]})")
     badE = PT.ensemble_mismatches(ref, got, rest)
     assert not badE, f"{name}: ensemble mismatches {badE}"
     return direct, rest
@@ -97,6 +102,18 @@ def test_thermal_parity_ragged(kernel):
     ex = (got["status"].astype(np.int64) & oracle.EXITED) != 0
     assert np.all(np.abs(r_atom[ex] - w.system.r0) < 1e-8 * w.system.r0)
     assert_parity(P, ref, got, f"thermal/{kernel}", min_direct=400)
+
+
+def test_fig4_energy_sweep_parity_ragged():
+    """Fig. 4 runs: r0 = 20,000 a0, collision energies log-uniform over 0.1 uK - 1 mK, random RF
+    phase, five atoms; 700 ids from an offset."""
+    w = W.fig4_energy()
+    w.system.max_steps = 2_000_000
+    id0 = 4_000_321
+    got = run(w, n=700, id0=id0)
+    P, ref = oracle_run(w, np.arange(id0, id0 + 700))
+    assert np.all(P["r0"] == 20_000.0)
+    assert_parity(P, ref, got, "fig4", min_direct=300)
 
 
 def test_plain_and_persistent_are_bitwise_identical():

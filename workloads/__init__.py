@@ -192,4 +192,29 @@ def fig3_thermal() -> Workload:
                     gen=gen)
 
 
+def fig4_energy(species=(0, 1, 2, 3, 4)) -> Workload:
+    """Collision-energy sweep (Fig. 4): head-on collisions of each atom with Yb+ from r0 = 20,000 a0,
+    q_x = 0.2, D_e = 1 K, random direction and RF phase, collision energy log-uniform over
+    0.1 uK - 1 mK (the paper takes 100 fixed energies; a continuous draw binned on the device in
+    log10(E / W0) is the same measurement on the axis of the threshold claim).  10^6 trajectories
+    per species."""
+    sys_ = System(r0=20_000.0)
+    gen = Generator(kind="sweep", seed=SEED_BASE + 14, species=list(species),
+                    E_range=(kelvin(0.1e-6), kelvin(1e-3)), q_list=[0.2], De_list=[kelvin(1.0)])
+    return Workload(name=f"fig4_energy_sweep_{len(species)}species", n=1_000_000 * len(species),
+                    system=sys_, species_names=list(SPECIES_ORDER), gen=gen)
+
+
+def fig4_inset() -> Workload:
+    """Fig. 4 inset: Yb+ - Li head-on at q_x = 0.1, 0.2, 0.3, 0.4 (Omega fixed) and eight collision
+    energies 0.1 - 2 uK, r0 = 20,000 a0, D_e = 1 K, random direction and RF phase; 32 cells,
+    10^4 trajectories each (cell = id mod 32, energy digit before q)."""
+    sys_ = System(r0=20_000.0)
+    gen = Generator(kind="sweep", seed=SEED_BASE + 15, species=[0],
+                    E_list=[kelvin(x * 1e-6) for x in (0.1, 0.2, 0.3, 0.5, 0.7, 1.0, 1.5, 2.0)],
+                    q_list=[0.1, 0.2, 0.3, 0.4], De_list=[kelvin(1.0)])
+    return Workload(name="fig4_inset_li_4q_8E", n=320_000, system=sys_, species_names=list(SPECIES_ORDER),
+                    gen=gen)
+
+
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
