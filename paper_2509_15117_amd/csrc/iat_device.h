@@ -50,6 +50,22 @@ constexpr double r1 = e3 * a31 + e4 * a41 + e5 * a51 + e6 * a61 + e7 * b1,
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 
+// The Nystrom tableau as one object.  Where a kernel's step uses kTab directly the coefficients
+// become instruction literals; a 64-bit literal has to be rebuilt in scalar registers at every use
+// (two scalar moves, each a wave issue slot), so the latency-bound four-lane tail instead holds a
+// copy in vector registers for the whole kernel (tab_in_registers).  The values are the same, so
+// the step gives the same bits either way.
+struct Tab {
+    double c2, c3, c4, c5;
+    double p31, p41, p42, p51, p52, p53, p61, p62, p63, p64;
+    double q1, q2, q3, q4, q5;
+    double b1, b3, b4, b5, b6;
+    double r1, r2, r3, r4, r5, r6;
+    double e1, e3, e4, e5, e6, e7;
+};
+constexpr Tab kTab = {c2,  c3,  c4,  c5,  p31, p41, p42, p51, p52, p53, p61, p62, p63, p64, q1, q2, q3, q4,
+                      q5,  b1,  b3,  b4,  b5,  b6,  r1,  r2,  r3,  r4,  r5,  r6,  e1, e3, e4, e5, e6, e7};
+
 // ---------------------------------------------------------------------------------------
 // Launch parameters (kernel argument block), all in internal units where it matters.
 // ---------------------------------------------------------------------------------------
@@ -318,42 +334,61 @@ __device__ __forceinline__ double acc_ion(double inv_mi, double s, double dk, do
     return -(s * dk) * inv_mi - (kA + qc * qr) * xi;
 }
 
+// A copy of the tableau in vector registers: the empty asm statements make each value opaque, so
+// the compiler keeps it in a register instead of folding it back into literals.
+__device__ __forceinline__ Tab tab_in_registers()
+{
+    Tab t = kTab;
+    double* v = &t.c2;
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(Tab) / sizeof(double)); ++k) asm volatile("" : "+v"(v[k]));
+    return t;
+}
+
 // Stage positions X_s = x + c_s h v + h^2 sum_j (A^2)_sj F_j, fifth-order solution and error.
-__device__ __forceinline__ double stage2(double x, double v, double h) { return x + (c2 * h) * v; }
-__device__ __forceinline__ double stage3(double x, double v, double h, double hh, double f1)
+__device__ __forceinline__ double stage2(double x, double v, double h, const Tab& T = kTab)
 {
-    return x + (c3 * h) * v + hh * (p31 * f1);
+    return x + (T.c2 * h) * v;
 }
-__device__ __forceinline__ double stage4(double x, double v, double h, double hh, double f1, double f2)
+__device__ __forceinline__ double stage3(double x, double v, double h, double hh, double f1, const Tab& T = kTab)
 {
-    return x + (c4 * h) * v + hh * (p41 * f1 + p42 * f2);
+    return x + (T.c3 * h) * v + hh * (T.p31 * f1);
 }
-__device__ __forceinline__ double stage5(double x, double v, double h, double hh, double f1, double f2, double f3)
+__device__ __forceinline__ double stage4(double x, double v, double h, double hh, double f1, double f2,
+                                         const Tab& T = kTab)
 {
-    return x + (c5 * h) * v + hh * (p51 * f1 + p52 * f2 + p53 * f3);
+    return x + (T.c4 * h) * v + hh * (T.p41 * f1 + T.p42 * f2);
+}
+__device__ __forceinline__ double stage5(double x, double v, double h, double hh, double f1, double f2, double f3,
+                                         const Tab& T = kTab)
+{
+    return x + (T.c5 * h) * v + hh * (T.p51 * f1 + T.p52 * f2 + T.p53 * f3);
 }
 __device__ __forceinline__ double stage6(double x, double v, double h, double hh, double f1, double f2, double f3,
-                                         double f4)
+                                         double f4, const Tab& T = kTab)
 {
-    return x + h * v + hh * (p61 * f1 + p62 * f2 + p63 * f3 + p64 * f4);
+    return x + h * v + hh * (T.p61 * f1 + T.p62 * f2 + T.p63 * f3 + T.p64 * f4);
 }
 __device__ __forceinline__ double sol_x(double x, double v, double h, double hh, double f1, double f2, double f3,
-                                        double f4, double f5)
+                                        double f4, double f5, const Tab& T = kTab)
 {
-    return x + h * v + hh * (q1 * f1 + q2 * f2 + q3 * f3 + q4 * f4 + q5 * f5);
+    return x + h * v + hh * (T.q1 * f1 + T.q2 * f2 + T.q3 * f3 + T.q4 * f4 + T.q5 * f5);
 }
-__device__ __forceinline__ double sol_v(double v, double h, double f1, double f3, double f4, double f5, double f6)
+__device__ __forceinline__ double sol_v(double v, double h, double f1, double f3, double f4, double f5, double f6,
+                                        const Tab& T = kTab)
 {
-    return v + h * (b1 * f1 + b3 * f3 + b4 * f4 + b5 * f5 + b6 * f6);
+    return v + h * (T.b1 * f1 + T.b3 * f3 + T.b4 * f4 + T.b5 * f5 + T.b6 * f6);
 }
-__device__ __forceinline__ double err_x(double hh, double f1, double f2, double f3, double f4, double f5, double f6)
+__device__ __forceinline__ double err_x(double hh, double f1, double f2, double f3, double f4, double f5, double f6,
+                                        const Tab& T = kTab)
 {
-    return hh * (r1 * f1 + r2 * f2 + r3 * f3 + r4 * f4 + r5 * f5 + r6 * f6);
+    return hh * (T.r1 * f1 + T.r2 * f2 + T.r3 * f3 + T.r4 * f4 + T.r5 * f5 + T.r6 * f6);
 }
-__device__ __forceinline__ double err_v(double h, double f1, double f3, double f4, double f5, double f6, double f7)
+__device__ __forceinline__ double err_v(double h, double f1, double f3, double f4, double f5, double f6, double f7,
+                                        const Tab& T = kTab)
 {
-    const double e = h * (e1 * f1 + e3 * f3 + e4 * f4 + e5 * f5 + e6 * f6);
-    return e + h * (e7 * f7);
+    const double e = h * (T.e1 * f1 + T.e3 * f3 + T.e4 * f4 + T.e5 * f5 + T.e6 * f6);
+    return e + h * (T.e7 * f7);
 }
 // |err_k| / (atol + rtol max(|y_k|, |y5_k|)) with a refined hardware reciprocal
 __device__ __forceinline__ double err_ratio(double e, double y, double y5, double rtol, double atol)
@@ -883,13 +918,13 @@ __device__ __forceinline__ int quad_or(int v)
 // Stage cosines for the four-lane form: the values of stage_cos, with its six polynomial
 // evaluations (the phase remainder and the five stage offsets) shared out over the quad's lanes
 // in two rounds and gathered with quad moves.
-__device__ __forceinline__ StageCos stage_cos4(double tau, double phase0, double h)
+__device__ __forceinline__ StageCos stage_cos4(double tau, double phase0, double h, const Tab& T = kTab)
 {
     const int l = __lane_id() & 3;
     double k;
     const double r = phase_reduce(tau + phase0, k);
-    const double a1 = l == 0 ? r : (l == 1 ? c2 * h : (l == 2 ? c3 * h : c4 * h));
-    const double a2 = (l & 1) ? h : c5 * h;
+    const double a1 = l == 0 ? r : (l == 1 ? T.c2 * h : (l == 2 ? T.c3 * h : T.c4 * h));
+    const double a2 = (l & 1) ? h : T.c5 * h;
     double cA, sA, cB, sB;
     small_sincos(a1, cA, sA);
     small_sincos(a2, cB, sB);
@@ -957,7 +992,7 @@ __device__ inline void traj4_start(const KParams& P, const Work& W, int64_t i, T
 // One attempted step of the four-lane form.  Returns the StepOutcome, or -1 when the trajectory
 // stopped before stepping (step cap, step underflow); h_used receives the step size tried.
 template <bool CE = false>
-__device__ __forceinline__ int traj4_step(const KParams& P, Traj4& T, double& h_used)
+__device__ __forceinline__ int traj4_step(const KParams& P, Traj4& T, double& h_used, const Tab& B = kTab)
 {
     double h;
     bool fin;
@@ -967,28 +1002,28 @@ __device__ __forceinline__ int traj4_step(const KParams& P, Traj4& T, double& h_
     const bool exiting = T.S.mode != 0;
     const int k = quad_axis();
     const double hh = h * h;
-    const StageCos C = stage_cos4(T.S.tau, T.L.phase0, h);
+    const StageCos C = stage_cos4(T.S.tau, T.L.phase0, h, B);
     double F2a, F2i, F3a, F3i, F4a, F4i, F5a, F5i, F6a, F6i;
-    accel4(P, T.L, k, C.c2, stage2(T.xa, T.va, h), stage2(T.xi, T.vi, h), F2a, F2i);
-    accel4(P, T.L, k, C.c3, stage3(T.xa, T.va, h, hh, T.F1a), stage3(T.xi, T.vi, h, hh, T.F1i), F3a, F3i);
-    accel4(P, T.L, k, C.c4, stage4(T.xa, T.va, h, hh, T.F1a, F2a), stage4(T.xi, T.vi, h, hh, T.F1i, F2i), F4a,
+    accel4(P, T.L, k, C.c2, stage2(T.xa, T.va, h, B), stage2(T.xi, T.vi, h, B), F2a, F2i);
+    accel4(P, T.L, k, C.c3, stage3(T.xa, T.va, h, hh, T.F1a, B), stage3(T.xi, T.vi, h, hh, T.F1i, B), F3a, F3i);
+    accel4(P, T.L, k, C.c4, stage4(T.xa, T.va, h, hh, T.F1a, F2a, B), stage4(T.xi, T.vi, h, hh, T.F1i, F2i, B), F4a,
            F4i);
-    accel4(P, T.L, k, C.c5, stage5(T.xa, T.va, h, hh, T.F1a, F2a, F3a),
-           stage5(T.xi, T.vi, h, hh, T.F1i, F2i, F3i), F5a, F5i);
-    accel4(P, T.L, k, C.c6, stage6(T.xa, T.va, h, hh, T.F1a, F2a, F3a, F4a),
-           stage6(T.xi, T.vi, h, hh, T.F1i, F2i, F3i, F4i), F6a, F6i);
-    const double x5a = sol_x(T.xa, T.va, h, hh, T.F1a, F2a, F3a, F4a, F5a);
-    const double x5i = sol_x(T.xi, T.vi, h, hh, T.F1i, F2i, F3i, F4i, F5i);
-    const double v5a = sol_v(T.va, h, T.F1a, F3a, F4a, F5a, F6a);
-    const double v5i = sol_v(T.vi, h, T.F1i, F3i, F4i, F5i, F6i);
+    accel4(P, T.L, k, C.c5, stage5(T.xa, T.va, h, hh, T.F1a, F2a, F3a, B),
+           stage5(T.xi, T.vi, h, hh, T.F1i, F2i, F3i, B), F5a, F5i);
+    accel4(P, T.L, k, C.c6, stage6(T.xa, T.va, h, hh, T.F1a, F2a, F3a, F4a, B),
+           stage6(T.xi, T.vi, h, hh, T.F1i, F2i, F3i, F4i, B), F6a, F6i);
+    const double x5a = sol_x(T.xa, T.va, h, hh, T.F1a, F2a, F3a, F4a, F5a, B);
+    const double x5i = sol_x(T.xi, T.vi, h, hh, T.F1i, F2i, F3i, F4i, F5i, B);
+    const double v5a = sol_v(T.va, h, T.F1a, F3a, F4a, F5a, F6a, B);
+    const double v5i = sol_v(T.vi, h, T.F1i, F3i, F4i, F5i, F6i, B);
     double en = 0.0, F7a = 0.0, F7i = 0.0;
     bool finite = true;
     if (!exiting) {
         accel4(P, T.L, k, C.c6, x5a, x5i, F7a, F7i);
-        const double ra = err_ratio(err_x(hh, T.F1a, F2a, F3a, F4a, F5a, F6a), T.xa, x5a, P.rtol, P.atol);
-        const double ri = err_ratio(err_x(hh, T.F1i, F2i, F3i, F4i, F5i, F6i), T.xi, x5i, P.rtol, P.atol);
-        const double rva = err_ratio(err_v(h, T.F1a, F3a, F4a, F5a, F6a, F7a), T.va, v5a, P.rtol, P.atol);
-        const double rvi = err_ratio(err_v(h, T.F1i, F3i, F4i, F5i, F6i, F7i), T.vi, v5i, P.rtol, P.atol);
+        const double ra = err_ratio(err_x(hh, T.F1a, F2a, F3a, F4a, F5a, F6a, B), T.xa, x5a, P.rtol, P.atol);
+        const double ri = err_ratio(err_x(hh, T.F1i, F2i, F3i, F4i, F5i, F6i, B), T.xi, x5i, P.rtol, P.atol);
+        const double rva = err_ratio(err_v(h, T.F1a, F3a, F4a, F5a, F6a, F7a, B), T.va, v5a, P.rtol, P.atol);
+        const double rvi = err_ratio(err_v(h, T.F1i, F3i, F4i, F5i, F6i, F7i, B), T.vi, v5i, P.rtol, P.atol);
         const int bad = quad_or((ratio_bad(ra) || ratio_bad(ri) || ratio_bad(rva) || ratio_bad(rvi)) ? 1 : 0);
         const int nonfin =
             quad_or((is_finite(x5a) && is_finite(x5i) && is_finite(v5a) && is_finite(v5i)) ? 0 : 1);
@@ -1029,10 +1064,10 @@ __device__ __forceinline__ int traj4_step(const KParams& P, Traj4& T, double& h_
 }
 
 template <bool CE = false>
-__device__ __forceinline__ void traj4_advance(const KParams& P, Traj4& T)
+__device__ __forceinline__ void traj4_advance(const KParams& P, Traj4& T, const Tab& B = kTab)
 {
     double h;
-    (void)traj4_step<CE>(P, T, h);
+    (void)traj4_step<CE>(P, T, h, B);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -173,6 +173,7 @@ __global__ void __launch_bounds__(256) k_integrate_tail(KParams P, Work W, Cont 
     int32_t resumed_at = 0, resumed_rhs = 0;
     uint64_t tail_rhs = 0, tail_done = 0;
     bool active = false, need = true;
+    const Tab B = tab_in_registers();
     for (;;) {
         const uint64_t mask = __ballot(need && leader);
         if (mask) {
@@ -192,7 +193,7 @@ __global__ void __launch_bounds__(256) k_integrate_tail(KParams P, Work W, Cont 
             }
         }
         if (!__any(active)) break;
-        if (active && !T.S.done) traj4_advance<CE>(P, T);
+        if (active && !T.S.done) traj4_advance<CE>(P, T, B);
         ++iters;
         if (active && T.S.done) {
             traj4_store(W, i, T, lane & 3);
