@@ -80,6 +80,20 @@ def test_validation_rejects_bad_arguments_without_gpu():
                     De_range=(1e-6, 1e-5))
     rc, msg = _call(batch=api.batch_struct(0, g), obs=_obs_dummy())
     assert rc == _abi.IAT_EINVAL and "species" in msg
+    th = W.fig3_thermal().gen
+    g = W.Generator(kind="thermal", species=[0], E_list=[1e-12], q_list=[0.2], De_list=[1e-6], T_ion=-1e-6)
+    rc, msg = _call(batch=api.batch_struct(0, g), obs=_obs_dummy())
+    assert rc == _abi.IAT_EINVAL and "T_ion" in msg
+    g = W.Generator(kind="thermal", species=[0], E_list=[1e-12], q_list=[0.0], De_list=[1e-6])
+    rc, msg = _call(batch=api.batch_struct(0, g), obs=_obs_dummy())
+    assert rc == _abi.IAT_EINVAL and "q_x" in msg
+    b = api.batch_struct(0, th)
+    b.y0 = 0x1000                                    # a device address the check never dereferences
+    rc, msg = _call(batch=b, obs=_obs_dummy())
+    assert rc == _abi.IAT_EINVAL and "y0" in msg
+    five = W.fig3_thermal().species()
+    rc, msg = _call(species=api.species_array(five), n_species=5, batch=api.batch_struct(0, th), obs=_obs_dummy())
+    assert rc == 0, msg
     s = api.system_struct(w.system)
     s.hmax = 1.0                                     # > pi/4: beyond an eighth of the RF period
     rc, msg = _call(system=s, obs=_obs_dummy())
