@@ -123,6 +123,7 @@ __global__ void __launch_bounds__(256) k_adj_forward(KParams P, Work W, AdjBuf B
         return;
     }
     double* R = B.rec + B.off[i] * kRec;
+    const Tab TB = tab_in_registers();     // latency-bound: coefficients held in registers
     Traj4 T;
     traj4_start(P, W, i, T);
     bool ok = true;
@@ -132,7 +133,7 @@ __global__ void __launch_bounds__(256) k_adj_forward(KParams P, Work W, AdjBuf B
     while (!T.S.done) {
         const double xa = T.xa, xi = T.xi, va = T.va, vi = T.vi, fa = T.F1a, fi = T.F1i, tau = T.S.tau;
         double h;
-        const int o = traj4_step(P, T, h);
+        const int o = traj4_step(P, T, h, TB);
         if (o == OUT_ACCEPT) {
             ++ncom;
             if (ncom % kSeg == 0) {
