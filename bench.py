@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--inflight", type=int, default=3,
                     help="also time this many whole passes in flight at once, one per stream (0: skip)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-kernel comparison run")
+    ap.add_argument("--no-critical-path", action="store_true",
+                    help="skip the longest trajectory's latency bound on the tail kernel")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "traffic.json"))
@@ -251,6 +253,31 @@ def pipelined(api, torch, w, passes, launch):
     print(f"[bench] {passes} passes in flight: {secs:.2f} s", file=sys.stderr, flush=True)
     return {"passes": passes, "streams": passes, "seconds": secs, "trajectories_per_s": passes * w.n / secs,
             "what": "independent whole passes in flight at once, one per stream; value stays the one-pass figure"}
+
+
+def critical_path(api, torch, w, tail_ms, budget=20000, cap=400_000):
+    """The tail kernel is latency-bound: it cannot end before the longest trajectory has run its
+    steps beyond the budget, one after another, at the per-step latency of a trajectory alone in the
+    four-lane form.  One more pass with step counters finds that trajectory; a bounded prefix of it
+    (`cap` accepted steps) timed alone gives the latency.  frac = that bound / the tail's duration."""
+    import copy
+    import ctypes
+    o = api.integrate_workload(w, counters=True)
+    steps = o["n_accept"].to(torch.int64) + o["n_reject"].to(torch.int64)
+    i = int(torch.argmax(steps).item())
+    n_steps = int(steps[i].item())
+    wl = copy.deepcopy(w)
+    wl.system.max_steps = cap
+    ms = (ctypes.c_float * 4)()
+    r = api.integrate_workload(wl, n=1, id0=i, counters=True, kernel="persistent", step_budget=1, kernel_ms=ms)
+    s1 = int(r["n_accept"].item() + r["n_reject"].item())
+    us = ms[2] * 1e3 / max(s1, 1)
+    bound_ms = max(n_steps - budget, 0) * us / 1e3
+    print(f"[bench] longest trajectory {i}: {n_steps} attempted steps, {us:.3f} us per step alone", file=sys.stderr,
+          flush=True)
+    return {"trajectory_id": i, "attempted_steps": n_steps, "lone_us_per_step": us,
+            "lone_sample_steps": s1, "tail_bound_ms": bound_ms, "tail_ms": tail_ms,
+            "frac": bound_ms / tail_ms if tail_ms > 0 else None}
 
 
 def timed_runs(api, torch, w, out, stats, steps, warmup, **launch):
@@ -458,6 +485,8 @@ def main():
                         "fp64_frac_peak": FLOP_PER_RHS * rp["rhs"] / rp["total_s"] / (FP64_PEAK_TFLOPS * 1e12),
                         "active_lane_fraction": rp["useful"] / max(rp["issued"], 1), "ms": rp["total_s"] * 1e3}
         res["speedup_vs_plain"] = traj_s / res["plain"]["trajectories_per_s"]
+    if args.kernel == "persistent" and not args.no_critical_path:
+        res["critical_path"] = critical_path(api, torch, w, r["phase_ms"][2])
     if args.inflight > 1:
         res["pipelined"] = pipelined(api, torch, w, args.inflight, launch)
     pk = api.fp64_peak()
