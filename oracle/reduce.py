@@ -99,7 +99,7 @@ def w0_hist(ids, workload, dE, status):
     for a sweep workload; the coordinates let a comparison recognise values that sit on a bin edge."""
     sysw = workload.system
     spec = workload.species()
-    if workload.gen.kind == "sweep":
+    if workload.gen.kind in ("sweep", "thermal"):      # thermal runs: E is the bath energy k_B T
         E, q, slot, sp = sweep_params(ids, workload)
         n_slots = len(workload.gen.species)
     else:

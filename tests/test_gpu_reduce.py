@@ -66,6 +66,31 @@ def test_reduce_cells_matches_oracle_and_accumulates():
     assert np.array_equal(again, got)
 
 
+def test_reduce_on_a_thermal_generator():
+    """Thermal runs (Fig. 3) share the sweep's cell digits and species slots; their W0 axis uses the
+    bath energy k_B T in place of the collision energy."""
+    w = W.fig3_thermal()
+    n, id0 = 60_007, 424_242
+    obs, dE, nb, st = synthetic_obs(n, 3)
+    print(f"reduce CELLS and W0_HIST: thermal generator, n={n}, id0={id0}", flush=True)
+    ids = np.arange(id0, id0 + n)
+    got = api.reduce_cells(w.system, w.species(), w.gen, n, obs, id0=id0).cpu().numpy()
+    ref = R.reduce_cells(ids, w.gen, dE, nb, st)
+    assert got.shape == (30, 5) and np.array_equal(got[:, [0, 1, 4]], ref[:, [0, 1, 4]])
+    abs1 = np.bincount(ids % 30, weights=np.abs(dE), minlength=30)
+    assert np.all(np.abs(got[:, 2] - ref[:, 2]) <= 1e-12 * abs1)
+    hw, hh = (t.cpu().numpy() for t in api.split_hist(api.reduce_hist(w.system, w.species(), w.gen, n, obs,
+                                                                       id0=id0)))
+    ref_w, ref_h, cw, ch = R.w0_hist(ids, w, dE, st)
+    assert hw.shape == ref_w.shape == (5, 64, 2)
+    _, _, slot, _ = R.sweep_params(ids, w)
+    for s in range(5):
+        for k in range(2):
+            sel = slot == s if k == 0 else (slot == s) & ((st & 1) != 0)
+            assert _hist_close(hw[s, :, k], ref_w[s, :, k], cw[sel], 64), (s, k)
+    assert _hist_close(hh, ref_h, ch, 256)
+
+
 def _hist_close(got, ref, coord, nbins, tol=1e-9):
     """got, ref: counts over the same axis; items whose coordinate lies within tol of an interior edge
     may sit in either adjacent bin."""
