@@ -563,9 +563,38 @@ __device__ inline bool warn_r0(const KParams& P, const TrajParams& tp, const dou
     return !(10.0 * fabs(V) < ek);
 }
 
+// The launch constants a step reads.  Where a kernel is short of scalar registers the compiler
+// reloads them from the kernel-argument block at every use (a scalar load and its wait); the
+// latency-bound four-lane tail keeps a copy in vector registers instead (step_k_in_registers).
+struct StepK {
+    double r0, r0sq, tau_max, rtol, atol, hmax, hmin, rb_ratio2;
+    int64_t max_steps;
+};
+__device__ __forceinline__ StepK step_k(const KParams& P)
+{
+    StepK k;
+    k.r0 = P.r0;
+    k.r0sq = P.r0sq;
+    k.tau_max = P.tau_max;
+    k.rtol = P.rtol;
+    k.atol = P.atol;
+    k.hmax = P.hmax;
+    k.hmin = P.hmin;
+    k.rb_ratio2 = P.rb_ratio2;
+    k.max_steps = P.max_steps;
+    return k;
+}
+__device__ __forceinline__ StepK step_k_in_registers(const KParams& P)
+{
+    StepK k = step_k(P);
+    asm volatile("" : "+v"(k.r0), "+v"(k.r0sq), "+v"(k.tau_max), "+v"(k.rtol), "+v"(k.atol));
+    asm volatile("" : "+v"(k.hmax), "+v"(k.hmin), "+v"(k.rb_ratio2), "+v"(k.max_steps));
+    return k;
+}
+
 // Step prologue shared by both forms: picks h and handles the stops that precede a step.
 // Returns false when the trajectory stopped.
-__device__ __forceinline__ bool step_prologue(const KParams& P, Scal& S, double& h, bool& fin)
+__device__ __forceinline__ bool step_prologue(const StepK& P, Scal& S, double& h, bool& fin)
 {
     fin = false;
     if (S.mode != 0) {
@@ -609,7 +638,7 @@ enum StepOutcome { OUT_SECANT_CONT = 0, OUT_SECANT_DONE, OUT_REJECT, OUT_NONFINI
 // start and of the new state when CE (else the separation is the exit geometry); fin: final step.
 // In secant mode only the exit radius of the new state is used.
 template <bool CE = false>
-__device__ __forceinline__ StepOutcome step_epilogue(const KParams& P, Scal& S, const Lane& L, double h, bool fin,
+__device__ __forceinline__ StepOutcome step_epilogue(const StepK& P, Scal& S, const Lane& L, double h, bool fin,
                                                      double en, bool finite, double rho_new, double s_new,
                                                      double w2, double e_prev = 0.0, double e_new = 0.0,
                                                      double se_new = 0.0)
@@ -809,9 +838,10 @@ __device__ __forceinline__ void traj1_store(const Work& W, int64_t i, const Traj
 template <bool CE = false>
 __device__ __forceinline__ void traj1_advance(const KParams& P, Traj1& T)
 {
+    const StepK K = step_k(P);
     double h;
     bool fin;
-    if (!step_prologue(P, T.S, h, fin)) return;
+    if (!step_prologue(K, T.S, h, fin)) return;
     const bool exiting = T.S.mode != 0;
     const double hh = h * h;
     const StageCos C = stage_cos(T.S.tau, T.L.phase0, h);
@@ -847,8 +877,8 @@ __device__ __forceinline__ void traj1_advance(const KParams& P, Traj1& T)
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             const double ev = err_v(h, T.F1[k], F3[k], F4[k], F5[k], F6[k], F7[k]);
-            const double rx = err_ratio(ex[k], T.x[k], x5[k], P.rtol, P.atol);
-            const double rv = err_ratio(ev, T.v[k], v5[k], P.rtol, P.atol);
+            const double rx = err_ratio(ex[k], T.x[k], x5[k], K.rtol, K.atol);
+            const double rv = err_ratio(ev, T.v[k], v5[k], K.rtol, K.atol);
             bad = bad || ratio_bad(rx) || ratio_bad(rv);
             m = fmax(m, fmax(rx, rv));
             finite = finite && is_finite(x5[k]) && is_finite(v5[k]);
@@ -866,7 +896,7 @@ __device__ __forceinline__ void traj1_advance(const KParams& P, Traj1& T)
         e_new = dot3(x5[0], x5[1], x5[2], x5[0], x5[1], x5[2]);
         se_new = dot3(x5[0], x5[1], x5[2], v5[0], v5[1], v5[2]);
     }
-    const StepOutcome o = step_epilogue<CE>(P, T.S, T.L, h, fin, en, finite, rho_new, s_new, ww, e_prev, e_new, se_new);
+    const StepOutcome o = step_epilogue<CE>(K, T.S, T.L, h, fin, en, finite, rho_new, s_new, ww, e_prev, e_new, se_new);
     if (o == OUT_SECANT_DONE || o == OUT_STOP_RFLOOR) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
@@ -921,10 +951,17 @@ __device__ __forceinline__ int quad_or(int v)
 __device__ __forceinline__ StageCos stage_cos4(double tau, double phase0, double h, const Tab& T = kTab)
 {
     const int l = __lane_id() & 3;
+    // per-lane offset coefficients, so each argument is one product: a1 = c_l h (lanes 1..3, lane 0
+    // takes the phase remainder), a2 = c5 h (lanes 0, 2) or 1.0 h = h (lanes 1, 3)
+    const double cl = l == 1 ? T.c2 : (l == 2 ? T.c3 : T.c4);
+    const double cl2 = (l & 1) ? 1.0 : T.c5;
     double k;
     const double r = phase_reduce(tau + phase0, k);
-    const double a1 = l == 0 ? r : (l == 1 ? T.c2 * h : (l == 2 ? T.c3 * h : T.c4 * h));
-    const double a2 = (l & 1) ? h : T.c5 * h;
+    // every lane reduces the phase: without this the compiler moves the reduction into a branch taken
+    // by lane 0 alone, and a quad then runs the lane cases one after another
+    asm volatile("" ::"v"(r));
+    const double a1 = l == 0 ? r : cl * h;
+    const double a2 = cl2 * h;
     double cA, sA, cB, sB;
     small_sincos(a1, cA, sA);
     small_sincos(a2, cB, sB);
@@ -992,12 +1029,13 @@ __device__ inline void traj4_start(const KParams& P, const Work& W, int64_t i, T
 // One attempted step of the four-lane form.  Returns the StepOutcome, or -1 when the trajectory
 // stopped before stepping (step cap, step underflow); h_used receives the step size tried.
 template <bool CE = false>
-__device__ __forceinline__ int traj4_step(const KParams& P, Traj4& T, double& h_used, const Tab& B = kTab)
+__device__ __forceinline__ int traj4_step_k(const KParams& P, const StepK& K, Traj4& T, double& h_used,
+                                            const Tab& B)
 {
     double h;
     bool fin;
     h_used = 0.0;
-    if (!step_prologue(P, T.S, h, fin)) return -1;
+    if (!step_prologue(K, T.S, h, fin)) return -1;
     h_used = h;
     const bool exiting = T.S.mode != 0;
     const int k = quad_axis();
@@ -1020,10 +1058,10 @@ __device__ __forceinline__ int traj4_step(const KParams& P, Traj4& T, double& h_
     bool finite = true;
     if (!exiting) {
         accel4(P, T.L, k, C.c6, x5a, x5i, F7a, F7i);
-        const double ra = err_ratio(err_x(hh, T.F1a, F2a, F3a, F4a, F5a, F6a, B), T.xa, x5a, P.rtol, P.atol);
-        const double ri = err_ratio(err_x(hh, T.F1i, F2i, F3i, F4i, F5i, F6i, B), T.xi, x5i, P.rtol, P.atol);
-        const double rva = err_ratio(err_v(h, T.F1a, F3a, F4a, F5a, F6a, F7a, B), T.va, v5a, P.rtol, P.atol);
-        const double rvi = err_ratio(err_v(h, T.F1i, F3i, F4i, F5i, F6i, F7i, B), T.vi, v5i, P.rtol, P.atol);
+        const double ra = err_ratio(err_x(hh, T.F1a, F2a, F3a, F4a, F5a, F6a, B), T.xa, x5a, K.rtol, K.atol);
+        const double ri = err_ratio(err_x(hh, T.F1i, F2i, F3i, F4i, F5i, F6i, B), T.xi, x5i, K.rtol, K.atol);
+        const double rva = err_ratio(err_v(h, T.F1a, F3a, F4a, F5a, F6a, F7a, B), T.va, v5a, K.rtol, K.atol);
+        const double rvi = err_ratio(err_v(h, T.F1i, F3i, F4i, F5i, F6i, F7i, B), T.vi, v5i, K.rtol, K.atol);
         const int bad = quad_or((ratio_bad(ra) || ratio_bad(ri) || ratio_bad(rva) || ratio_bad(rvi)) ? 1 : 0);
         const int nonfin =
             quad_or((is_finite(x5a) && is_finite(x5i) && is_finite(v5a) && is_finite(v5i)) ? 0 : 1);
@@ -1046,7 +1084,7 @@ __device__ __forceinline__ int traj4_step(const KParams& P, Traj4& T, double& h_
         e_new = dot3(a0, a1, a2, a0, a1, a2);
         se_new = dot3(a0, a1, a2, u0, u1, u2);
     }
-    const StepOutcome o = step_epilogue<CE>(P, T.S, T.L, h, fin, en, finite, rho_new, s_new, ww, e_prev, e_new, se_new);
+    const StepOutcome o = step_epilogue<CE>(K, T.S, T.L, h, fin, en, finite, rho_new, s_new, ww, e_prev, e_new, se_new);
     if (o == OUT_SECANT_DONE || o == OUT_STOP_RFLOOR) {
         T.xa = x5a;
         T.xi = x5i;
@@ -1062,12 +1100,23 @@ __device__ __forceinline__ int traj4_step(const KParams& P, Traj4& T, double& h_
     }
     return (int)o;
 }
+template <bool CE = false>
+__device__ __forceinline__ int traj4_step(const KParams& P, Traj4& T, double& h_used, const Tab& B = kTab)
+{
+    return traj4_step_k<CE>(P, step_k(P), T, h_used, B);
+}
 
 template <bool CE = false>
 __device__ __forceinline__ void traj4_advance(const KParams& P, Traj4& T, const Tab& B = kTab)
 {
     double h;
     (void)traj4_step<CE>(P, T, h, B);
+}
+template <bool CE = false>
+__device__ __forceinline__ void traj4_advance_k(const KParams& P, const StepK& K, Traj4& T, const Tab& B)
+{
+    double h;
+    (void)traj4_step_k<CE>(P, K, T, h, B);
 }
 
 // ---------------------------------------------------------------------------------------

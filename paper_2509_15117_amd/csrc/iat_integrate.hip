@@ -174,6 +174,7 @@ __global__ void __launch_bounds__(256) k_integrate_tail(KParams P, Work W, Cont 
     uint64_t tail_rhs = 0, tail_done = 0;
     bool active = false, need = true;
     const Tab B = tab_in_registers();
+    const StepK K = step_k_in_registers(P);
     for (;;) {
         const uint64_t mask = __ballot(need && leader);
         if (mask) {
@@ -193,7 +194,7 @@ __global__ void __launch_bounds__(256) k_integrate_tail(KParams P, Work W, Cont 
             }
         }
         if (!__any(active)) break;
-        if (active && !T.S.done) traj4_advance<CE>(P, T, B);
+        if (active && !T.S.done) traj4_advance_k<CE>(P, K, T, B);
         ++iters;
         if (active && T.S.done) {
             traj4_store(W, i, T, lane & 3);

@@ -81,7 +81,8 @@ __device__ __forceinline__ void tan4_advance(const KParams& P, Traj4& T, Tan4& D
 {
     double h;
     bool fin;
-    if (!step_prologue(P, T.S, h, fin)) return;
+    const StepK K = step_k(P);
+    if (!step_prologue(K, T.S, h, fin)) return;
     const bool exiting = T.S.mode != 0;
     const int k = quad_axis();
     const double hh = h * h;
@@ -114,10 +115,10 @@ __device__ __forceinline__ void tan4_advance(const KParams& P, Traj4& T, Tan4& D
     bool finite = true;
     if (!exiting) {
         accel4_tan(P, T.L, k, col, inv_De, ff, C.c6, x5a, x5i, y5a, y5i, F7a, F7i, G7a, G7i);
-        const double ra = err_ratio(err_x(hh, T.F1a, F2a, F3a, F4a, F5a, F6a), T.xa, x5a, P.rtol, P.atol);
-        const double ri = err_ratio(err_x(hh, T.F1i, F2i, F3i, F4i, F5i, F6i), T.xi, x5i, P.rtol, P.atol);
-        const double rva = err_ratio(err_v(h, T.F1a, F3a, F4a, F5a, F6a, F7a), T.va, v5a, P.rtol, P.atol);
-        const double rvi = err_ratio(err_v(h, T.F1i, F3i, F4i, F5i, F6i, F7i), T.vi, v5i, P.rtol, P.atol);
+        const double ra = err_ratio(err_x(hh, T.F1a, F2a, F3a, F4a, F5a, F6a), T.xa, x5a, K.rtol, K.atol);
+        const double ri = err_ratio(err_x(hh, T.F1i, F2i, F3i, F4i, F5i, F6i), T.xi, x5i, K.rtol, K.atol);
+        const double rva = err_ratio(err_v(h, T.F1a, F3a, F4a, F5a, F6a, F7a), T.va, v5a, K.rtol, K.atol);
+        const double rvi = err_ratio(err_v(h, T.F1i, F3i, F4i, F5i, F6i, F7i), T.vi, v5i, K.rtol, K.atol);
         const int bad = quad_or((ratio_bad(ra) || ratio_bad(ri) || ratio_bad(rva) || ratio_bad(rvi)) ? 1 : 0);
         const int nonfin =
             quad_or((is_finite(x5a) && is_finite(x5i) && is_finite(v5a) && is_finite(v5i)) ? 0 : 1);
@@ -131,7 +132,7 @@ __device__ __forceinline__ void tan4_advance(const KParams& P, Traj4& T, Tan4& D
     const double rho_new = dot3(d0, d1, d2, d0, d1, d2);
     const double s_new = dot3(d0, d1, d2, w0, w1, w2);
     const double ww = dot3(w0, w1, w2, w0, w1, w2);
-    const StepOutcome o = step_epilogue(P, T.S, T.L, h, fin, en, finite, rho_new, s_new, ww);
+    const StepOutcome o = step_epilogue(K, T.S, T.L, h, fin, en, finite, rho_new, s_new, ww);
     if (o == OUT_SECANT_CONT || o == OUT_SECANT_DONE) {
         // tangent of the latest secant iterate RK5(y_n, h*) with h* frozen
         ex_xa = y5a;
