@@ -318,19 +318,29 @@ class ScatteringObservables(torch.autograd.Function):
 
 def run_chunks(w, *, n: Optional[int] = None, chunk: int = 1 << 22, n_streams: int = 4, kernel="persistent",
                cells: bool = False, hist: bool = False, stats: Optional[torch.Tensor] = None, progress=None,
-               **launch):
+               sample=None, **launch):
     """Integrate ids [0, n) of a workloads.Workload in chunks of `chunk` ids spread round-robin over
     `n_streams` streams (default priority), reducing each chunk on its stream: per-cell sums (cells=True,
     sweeps) and the W0 / heating histograms (hist=True).  Only the reductions are kept.  While one
     chunk's long-lived complexes finish in its tail kernel, the next chunks run on the other streams.
     Returns {'cells': (n_cells, 5), 'hist': flat histogram} (device tensors, summed over streams).
-    progress(c, n_chunks): called on the host as chunk c completes (in chunk order)."""
+    progress(c, n_chunks): called on the host as chunk c completes (in chunk order).
+    sample: optional sorted global ids whose per-trajectory outputs (with step counters and final
+    states) are copied out of their chunk before its buffers are reused: res['sample']."""
     n = w.n if n is None else n
     dev = torch.device("cuda", torch.cuda.current_device())
     cur = torch.cuda.current_stream()
     streams = [torch.cuda.Stream(device=dev) for _ in range(max(1, n_streams))]
     m = min(chunk, n)
-    bufs = [alloc_obs(m, dev, counters=False) for _ in streams]
+    want = sample is not None
+    bufs = [alloc_obs(m, dev, counters=want, y_final=want) for _ in streams]
+    if want:
+        ids_h = torch.as_tensor(sample, dtype=torch.int64).cpu()
+        if len(ids_h) and (bool((ids_h[1:] < ids_h[:-1]).any()) or int(ids_h[0]) < 0 or int(ids_h[-1]) >= n):
+            raise ValueError("sample must be sorted ids in [0, n)")
+        ids_d = ids_h.to(dev)
+        s_out = {k: torch.empty((12, len(ids_h)) if k == "y_final" else (len(ids_h),), dtype=v.dtype, device=dev)
+                 for k, v in bufs[0].items()}
     slots = len(w.gen.species) if w.gen.kind in ("sweep", "thermal") else 1
     c_out = [torch.zeros(n_cells(w.gen), 5, dtype=torch.float64, device=dev) for _ in streams] if cells else None
     h_out = ([torch.zeros(slots * 2 * _abi.W0_BINS + _abi.HEAT_BINS, dtype=torch.float64, device=dev)
@@ -348,6 +358,17 @@ def run_chunks(w, *, n: Optional[int] = None, chunk: int = 1 << 22, n_streams: i
             reduce_cells(w.system, w.species(), w.gen, cnt, obs, id0=id0, out=c_out[k], stream=streams[k])
         if hist:
             reduce_hist(w.system, w.species(), w.gen, cnt, obs, id0=id0, out=h_out[k], stream=streams[k])
+        if want:
+            a = int(torch.searchsorted(ids_h, torch.tensor(id0)))
+            b = int(torch.searchsorted(ids_h, torch.tensor(id0 + cnt)))
+            if b > a:
+                with torch.cuda.stream(streams[k]):
+                    loc = ids_d[a:b] - id0
+                    for key, v in obs.items():
+                        if key == "y_final":
+                            s_out[key][:, a:b] = v.index_select(1, loc)
+                        else:
+                            s_out[key][a:b] = v.index_select(0, loc)
         if progress is not None:
             ev = torch.cuda.Event()
             ev.record(streams[k])
@@ -362,6 +383,11 @@ def run_chunks(w, *, n: Optional[int] = None, chunk: int = 1 << 22, n_streams: i
         res["cells"] = torch.stack(c_out).sum(0)
     if hist:
         res["hist"] = torch.stack(h_out).sum(0)
+    if want:
+        res["sample"] = s_out
+        for v in s_out.values():
+            for s in streams:
+                v.record_stream(s)
     for b in bufs:               # the buffers were used on the side streams
         for v in b.values():
             for s in streams:
