@@ -176,7 +176,10 @@ typedef struct {
                                  trajectory is suspended and finished by four lanes (one
                                  per axis) to cut the latency of long-lived complexes;
                                  0 = default (20000), -1 = never                         */
-    int32_t reserved;
+    int32_t max_suspended;    /* PERSISTENT: at most this many trajectories are suspended in
+                                 one call (continuation records of 248 B each, allocated
+                                 with the call's workspace); the others finish in the
+                                 one-lane kernel.  0 = min(n, 2^23)                      */
     uint64_t* stats;
     float* kernel_ms;
 } iat_launch;

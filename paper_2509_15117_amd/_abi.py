@@ -59,7 +59,7 @@ class Obs(ctypes.Structure):
 class Launch(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("refill_every", ctypes.c_int32), ("step_budget", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("stats", _vp), ("kernel_ms", _vp)]
+                ("max_suspended", ctypes.c_int32), ("stats", _vp), ("kernel_ms", _vp)]
 
 
 _P = ctypes.POINTER

@@ -111,12 +111,13 @@ def batch_struct(n: int, gen, arrays: Optional[Dict[str, torch.Tensor]] = None,
 
 
 def launch_struct(kernel="persistent", block=0, blocks_per_cu=0, refill_every=0, step_budget=0,
-                  stats: Optional[torch.Tensor] = None, kernel_ms=None) -> _abi.Launch:
+                  stats: Optional[torch.Tensor] = None, kernel_ms=None, max_suspended=0) -> _abi.Launch:
     """kernel_ms: optional host ctypes float[4] for the phase durations (the call then waits)."""
     L = _abi.Launch()
     L.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     L.block, L.blocks_per_cu, L.refill_every = block, blocks_per_cu, refill_every
     L.step_budget = step_budget
+    L.max_suspended = max_suspended
     L.stats = _ptr(stats)
     L.kernel_ms = None if kernel_ms is None else ctypes.cast(kernel_ms, ctypes.c_void_p)
     return L
@@ -124,7 +125,7 @@ def launch_struct(kernel="persistent", block=0, blocks_per_cu=0, refill_every=0,
 
 def integrate(system, species, gen, n: int, *, arrays=None, y0=None, id0=None, kernel="persistent", block=0,
               blocks_per_cu=0, refill_every=0, step_budget=0, y_final=False, counters=True, stats=None, out=None,
-              stream=None, device=None, kernel_ms=None) -> Dict[str, torch.Tensor]:
+              stream=None, device=None, kernel_ms=None, max_suspended=0) -> Dict[str, torch.Tensor]:
     """Integrate n trajectories on the current GPU; returns device tensors of the observables.
 
     system / gen: objects with the fields of workloads.System / workloads.Generator.
@@ -139,7 +140,7 @@ def integrate(system, species, gen, n: int, *, arrays=None, y0=None, id0=None, k
     sp = species_array(species)
     b = batch_struct(n, gen, arrays, y0, id0)
     o = obs_struct(out)
-    la = launch_struct(kernel, block, blocks_per_cu, refill_every, step_budget, stats, kernel_ms)
+    la = launch_struct(kernel, block, blocks_per_cu, refill_every, step_budget, stats, kernel_ms, max_suspended)
     rc = L.iat_integrate(ctypes.byref(sysv), sp, len(species), ctypes.byref(b), ctypes.byref(o), ctypes.byref(la),
                          None, 0, _stream_handle(stream))
     _abi.check(rc)

@@ -243,6 +243,7 @@ int resolve_launch(const iat_launch* launch, iat_launch* out)
     if (L.refill_every < 1 || L.refill_every > 4096)
         return set_error(IAT_EINVAL, "launch.refill_every must be in [1, 4096]");
     if (L.step_budget < -1) return set_error(IAT_EINVAL, "launch.step_budget must be >= -1");
+    if (L.max_suspended < 0) return set_error(IAT_EINVAL, "launch.max_suspended must be >= 0");
     *out = L;
     return 0;
 }

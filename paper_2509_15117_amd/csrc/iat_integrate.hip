@@ -276,7 +276,8 @@ extern "C" int iat_integrate(const iat_system* sys, const iat_species* species, 
     int64_t cap = 0;
     if (L.kernel == IAT_KERNEL_PERSISTENT) {
         P.budget = L.step_budget > 0 ? L.step_budget : (L.step_budget == 0 ? kDefaultBudget : 0);
-        cap = P.budget > 0 ? std::min<int64_t>(n, kMaxSuspended) : 0;
+        const int64_t lim = L.max_suspended > 0 ? std::min<int64_t>(L.max_suspended, kMaxSuspended) : kMaxSuspended;
+        cap = P.budget > 0 ? std::min<int64_t>(n, lim) : 0;
     }
     // one stream-ordered block: queue counters | work buffer | continuation records
     const size_t rec = 26 * sizeof(double) + 8 * sizeof(int32_t) + sizeof(int64_t);

@@ -124,7 +124,8 @@ def test_plain_and_persistent_are_bitwise_identical():
     for w, n in ((W.config1(), 64), (W.config3(), 3001), (thermal, 2001)):
         a = run(w, n=n, kernel="plain")
         for kw in (dict(block=256), dict(block=64, refill_every=4), dict(block=128, blocks_per_cu=1),
-                   dict(step_budget=-1), dict(step_budget=7), dict(step_budget=500, refill_every=3)):
+                   dict(step_budget=-1), dict(step_budget=7), dict(step_budget=500, refill_every=3),
+                   dict(step_budget=7, max_suspended=5)):          # most cannot be suspended
             b = run(w, n=n, kernel="persistent", **kw)
             for k in a:
                 assert np.array_equal(a[k], b[k], equal_nan=True), (w.name, kw, k)
