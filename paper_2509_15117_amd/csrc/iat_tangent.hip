@@ -76,12 +76,12 @@ __device__ __forceinline__ void tan_rescale(Tan4& D)
 
 // One attempted step of the four-lane primal with its tangent column.  Returns through the
 // tangent arguments the column at the step end (only committed by the caller's logic below).
-__device__ __forceinline__ void tan4_advance(const KParams& P, Traj4& T, Tan4& D, int col, double inv_De,
-                                             double& ex_xa, double& ex_xi, double& ex_va, double& ex_vi)
+__device__ __forceinline__ void tan4_advance(const KParams& P, const StepK& K, Traj4& T, Tan4& D, int col,
+                                             double inv_De, double& ex_xa, double& ex_xi, double& ex_va,
+                                             double& ex_vi)
 {
     double h;
     bool fin;
-    const StepK K = step_k(P);
     if (!step_prologue(K, T.S, h, fin)) return;
     const bool exiting = T.S.mode != 0;
     const int k = quad_axis();
@@ -216,7 +216,8 @@ __global__ void __launch_bounds__(256) k_tangent(KParams P, Work W, TanOut O)
         T.S.s_prev = dot3(d0, d1, d2, w0, w1, w2);
     }
     double ex_xa = 0.0, ex_xi = 0.0, ex_va = 0.0, ex_vi = 0.0;
-    while (!T.S.done) tan4_advance(P, T, D, col, inv_De, ex_xa, ex_xi, ex_va, ex_vi);
+    const StepK K = step_k_in_registers(P);      // latency-bound: launch constants held in registers
+    while (!T.S.done) tan4_advance(P, K, T, D, col, inv_De, ex_xa, ex_xi, ex_va, ex_vi);
     // uncorrected stability matrix (columns 0..11), scaled by 2^-exp2s per column
     if (O.Phi && q < 12 && kk < 3) {
         double* Ph = O.Phi + (size_t)i * 144;
