@@ -155,19 +155,19 @@ def test_full_size_grid_sampled_against_oracle():
     assert_parity(P, ref, sub, "config2-sampled", min_direct=10)
 
 
-@pytest.mark.parametrize("config", [3, 5])
-def test_full_size_chunked_sampled_against_oracle(config):
+@pytest.mark.parametrize("which", ["sweep_1.2e7", "stream_1e8"])
+def test_full_size_chunked_sampled_against_oracle(which):
     """The 1.2e7 sweep and the 1e8 stream at full size, in the benchmark's launch configuration (the
     job split over two streams, reductions on the device): 96 seeded ids copied out of their chunks
     and checked one by one (direct) or in ensemble; the reductions count every trajectory once."""
-    w = W.CONFIGS[config]()
+    sweep = which.startswith("sweep")
+    w = W.config3() if sweep else W.config5()
     n = w.n
-    ids = np.sort(np.random.default_rng(config).choice(n, size=96, replace=False))
-    print(f"config{config}: n={n} in two chunks on two streams, 96 sampled ids", flush=True)
-    res = api.run_chunks(w, n=n, chunk=-(-n // 2), n_streams=2, cells=config == 3, hist=config == 5,
-                         sample=ids)
+    ids = np.sort(np.random.default_rng(3 if sweep else 5).choice(n, size=96, replace=False))
+    print(f"{w.name}: n={n} in two chunks on two streams, 96 sampled ids", flush=True)
+    res = api.run_chunks(w, n=n, chunk=-(-n // 2), n_streams=2, cells=sweep, hist=not sweep, sample=ids)
     got = PT.to_numpy(res["sample"])
-    if config == 3:
+    if sweep:
         assert res["cells"][:, 0].sum().item() == n
     else:
         assert api.split_hist(res["hist"])[1].sum().item() == n
@@ -177,10 +177,10 @@ def test_full_size_chunked_sampled_against_oracle(config):
     P["max_steps"] = 2_000_000
     ref = oracle.integrate(P)
     keep = np.where((got["n_accept"] < 2_000_000) & ((ref["status"] & oracle.MAX_STEPS) == 0))[0]
-    print(f"config{config}: {96 - len(keep)} sampled complexes beyond 2e6 steps left out", flush=True)
+    print(f"{w.name}: {96 - len(keep)} sampled complexes beyond 2e6 steps left out", flush=True)
     assert len(keep) >= 90
     sub = {k: (v[:, keep] if k == "y_final" else v[keep]) for k, v in got.items()}
-    assert_parity(P[keep], ref[keep], sub, f"config{config}-sampled", min_direct=10)
+    assert_parity(P[keep], ref[keep], sub, f"{w.name}-sampled", min_direct=10)
 
 
 def _edge_system(**over):
