@@ -594,7 +594,7 @@ __device__ __forceinline__ StepK step_k_in_registers(const KParams& P)
 
 // Step prologue shared by both forms: picks h and handles the stops that precede a step.
 // Returns false when the trajectory stopped.
-__device__ __forceinline__ bool step_prologue(const StepK& P, Scal& S, double& h, bool& fin)
+__device__ __forceinline__ bool step_prologue(const StepK& K, Scal& S, double& h, bool& fin)
 {
     fin = false;
     if (S.mode != 0) {
@@ -603,17 +603,17 @@ __device__ __forceinline__ bool step_prologue(const StepK& P, Scal& S, double& h
         h = h < 0.0 ? 0.0 : (h > S.h ? S.h : h);
         return true;
     }
-    if (S.nacc >= P.max_steps) {
+    if (S.nacc >= K.max_steps) {
         S.status |= IAT_ST_MAX_STEPS;
         S.done = 1;
         return false;
     }
     h = S.h;
-    if (h >= P.tau_max - S.tau) {
-        h = P.tau_max - S.tau;
+    if (h >= K.tau_max - S.tau) {
+        h = K.tau_max - S.tau;
         fin = true;
     }
-    if (!fin && h < P.hmin) {
+    if (!fin && h < K.hmin) {
         S.status |= IAT_ST_H_UNDERFLOW;
         S.done = 1;
         return false;
@@ -638,14 +638,14 @@ enum StepOutcome { OUT_SECANT_CONT = 0, OUT_SECANT_DONE, OUT_REJECT, OUT_NONFINI
 // start and of the new state when CE (else the separation is the exit geometry); fin: final step.
 // In secant mode only the exit radius of the new state is used.
 template <bool CE = false>
-__device__ __forceinline__ StepOutcome step_epilogue(const StepK& P, Scal& S, const Lane& L, double h, bool fin,
+__device__ __forceinline__ StepOutcome step_epilogue(const StepK& K, Scal& S, const Lane& L, double h, bool fin,
                                                      double en, bool finite, double rho_new, double s_new,
                                                      double w2, double e_prev = 0.0, double e_new = 0.0,
                                                      double se_new = 0.0)
 {
     if (S.mode != 0) {
         S.nrhs += 5;
-        const double g2 = sqrt(CE ? e_new : rho_new) - P.r0;
+        const double g2 = sqrt(CE ? e_new : rho_new) - K.r0;
         S.rho_prev = S.sx1;
         S.s_prev = S.sg1;
         S.sx1 = h;
@@ -671,9 +671,9 @@ __device__ __forceinline__ StepOutcome step_epilogue(const StepK& P, Scal& S, co
         S.done = 1;
         return OUT_NONFINITE;
     }
-    const double tau_new = fin ? P.tau_max : S.tau + h;
+    const double tau_new = fin ? K.tau_max : S.tau + h;
     // bounce: periapsis of the relative motion inside r_b
-    if (S.s_prev < 0.0 && s_new >= 0.0 && fmin(S.rho_prev, rho_new) < L.rm2 * P.rb_ratio2) {
+    if (S.s_prev < 0.0 && s_new >= 0.0 && fmin(S.rho_prev, rho_new) < L.rm2 * K.rb_ratio2) {
         if (S.nb == 0) S.tau_first = tau_new;
         S.tau_last = tau_new;
         S.nb++;
@@ -686,13 +686,13 @@ __device__ __forceinline__ StepOutcome step_epilogue(const StepK& P, Scal& S, co
         return OUT_STOP_RFLOOR;
     }
     const double ex_prev = CE ? e_prev : S.rho_prev, ex_new = CE ? e_new : rho_new;
-    if (ex_prev <= P.r0sq && ex_new > P.r0sq && (CE ? se_new : s_new) > 0.0) {
+    if (ex_prev <= K.r0sq && ex_new > K.r0sq && (CE ? se_new : s_new) > 0.0) {
         // keep y_n; the next four steps are secant iterates, (x0, g0) kept in (rho_prev, s_prev)
         S.mode = 1;
-        S.s_prev = sqrt(ex_prev) - P.r0;
+        S.s_prev = sqrt(ex_prev) - K.r0;
         S.rho_prev = 0.0;
         S.sx1 = h;
-        S.sg1 = sqrt(ex_new) - P.r0;
+        S.sg1 = sqrt(ex_new) - K.r0;
         S.h = h;
         return OUT_ENTER_EXIT;
     }
@@ -705,7 +705,7 @@ __device__ __forceinline__ StepOutcome step_epilogue(const StepK& P, Scal& S, co
         S.h = h;
         return OUT_TMAX;
     }
-    S.h = fmin(P.hmax, h * step_factor(en, S.last_rej != 0));
+    S.h = fmin(K.hmax, h * step_factor(en, S.last_rej != 0));
     S.last_rej = 0;
     return OUT_ACCEPT;
 }
