@@ -304,12 +304,13 @@ extern "C" int iat_integrate(const iat_system* sys, const iat_species* species, 
     timer.mark(1);
     // thermal runs leave through the start sphere about the trap centre (CE kernels)
     const bool ce = batch->gen.kind == IAT_GEN_THERMAL;
+    hipError_t launch_err = hipSuccess;
     const void* k_plain = ce ? (const void*)k_integrate_plain<true> : (const void*)k_integrate_plain<false>;
     const void* k_pers = ce ? (const void*)k_integrate_persistent<true> : (const void*)k_integrate_persistent<false>;
     const void* k_tail = ce ? (const void*)k_integrate_tail<true> : (const void*)k_integrate_tail<false>;
     if (L.kernel == IAT_KERNEL_PLAIN) {
         void* args[] = {&P, &W};
-        (void)hipLaunchKernel(k_plain, dim3((unsigned)((n + L.block - 1) / L.block)), dim3(L.block), args, 0, st);
+        launch_err = hipLaunchKernel(k_plain, dim3((unsigned)((n + L.block - 1) / L.block)), dim3(L.block), args, 0, st);
     } else {
         int per_cu = L.blocks_per_cu;
         if (per_cu == 0) {
@@ -320,7 +321,7 @@ extern "C" int iat_integrate(const iat_system* sys, const iat_species* species, 
         const int64_t need = (n + L.block - 1) / L.block;
         if (blocks > need) blocks = need;
         void* args[] = {&P, &W, &q, &C};
-        (void)hipLaunchKernel(k_pers, dim3((unsigned)blocks), dim3(L.block), args, 0, st);
+        launch_err = hipLaunchKernel(k_pers, dim3((unsigned)blocks), dim3(L.block), args, 0, st);
         timer.mark(2);
         if (cap > 0) {
             int per_cu4 = 1;
@@ -330,7 +331,8 @@ extern "C" int iat_integrate(const iat_system* sys, const iat_species* species, 
             const int64_t need4 = (4 * cap + 255) / 256;
             if (blocks4 > need4) blocks4 = need4;
             void* args4[] = {&P, &W, &C};
-            (void)hipLaunchKernel(k_tail, dim3((unsigned)blocks4), dim3(256), args4, 0, st);
+            const hipError_t e4 = hipLaunchKernel(k_tail, dim3((unsigned)blocks4), dim3(256), args4, 0, st);
+            if (launch_err == hipSuccess) launch_err = e4;
         }
     }
     if (L.kernel == IAT_KERNEL_PLAIN) timer.mark(2);
@@ -339,6 +341,7 @@ extern "C" int iat_integrate(const iat_system* sys, const iat_species* species, 
     timer.mark(4);
     if (hipFreeAsync(ws, st) != hipSuccess) return set_error(IAT_EHIP, "hipFreeAsync failed");
     hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = launch_err;
     if (e != hipSuccess) return set_error(IAT_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
     return timer.finish();
 }
