@@ -240,3 +240,47 @@ def test_arrays_mode_matches_grid_mode():
     b = run(w)
     for k in a:
         assert np.array_equal(a[k], b[k]), k
+
+
+def test_trap_off_two_body_invariants_on_the_gpu():
+    """Independent of the oracle: with the trap off (a = q = 0) the ion-atom pair is an isolated
+    two-body system, so the GPU's final states must conserve the energy (kinetic + C8/r^8 - C4/r^4),
+    the angular momentum and the uniform motion of the centre of mass, here at rtol 1e-12 to 1e-10
+    of the well depth and of m_a r0 v0, for head-on and off-axis starts."""
+    w = W.config1()
+    w.system.q_x = 0.0
+    w.system.a_x = 0.0
+    w.system.rtol, w.system.atol = 1e-12, 1e-14
+    m_a, C4 = w.species()[0]
+    m_i, De, r0 = w.system.m_ion, w.system.De, w.system.r0
+    C8 = C4 * C4 / (4.0 * De)
+    v0 = math.sqrt(2.0 * w.system.E / m_a)
+    bs = [0.0, 300.0, 700.0, 1500.0, 3000.0, 4500.0]
+    y0 = np.zeros((12, len(bs)))
+    for j, b in enumerate(bs):
+        y0[0:3, j] = [b, 0.0, math.sqrt(r0 ** 2 - b ** 2)]
+        y0[6:9, j] = [0.0, 0.0, -v0]
+    out = api.integrate(w.system, w.species(), W.Generator(kind="arrays"), len(bs),
+                        y0=torch.from_numpy(y0).to("cuda"), y_final=True)
+    torch.cuda.synchronize()
+    got = PT.to_numpy(out)
+    assert np.all(got["status"].astype(np.int64) & oracle.EXITED)
+
+    def energy(y):
+        d = y[0:3] - y[3:6]
+        r2 = d @ d
+        return 0.5 * m_a * y[6:9] @ y[6:9] + 0.5 * m_i * y[9:12] @ y[9:12] + C8 / r2 ** 4 - C4 / r2 ** 2
+
+    def angmom(y):
+        return m_a * np.cross(y[0:3], y[6:9]) + m_i * np.cross(y[3:6], y[9:12])
+
+    M = m_a + m_i
+    for j in range(len(bs)):
+        a, f = y0[:, j], got["y_final"][:, j]
+        dE = abs(energy(f) - energy(a)) / De
+        dL = np.abs(angmom(f) - angmom(a)).max() / (m_a * r0 * v0)
+        V = (m_a * a[6:9] + m_i * a[9:12]) / M
+        R = (m_a * f[0:3] + m_i * f[3:6]) / M - (m_a * a[0:3] + m_i * a[3:6]) / M - V * got["t_dwell"][j]
+        print(f"b = {bs[j]:6.0f} a0: bounces {got['n_bounce'][j]}, energy drift {dE:.1e} De, "
+              f"angular momentum {dL:.1e}, centre of mass {np.abs(R).max() / r0:.1e} r0", flush=True)
+        assert dE < 1e-10 and dL < 1e-10 and np.abs(R).max() < 1e-9 * r0
