@@ -98,3 +98,26 @@ def test_validation_rejects_bad_arguments_without_gpu():
     s.hmax = 1.0                                     # > pi/4: beyond an eighth of the RF period
     rc, msg = _call(system=s, obs=_obs_dummy())
     assert rc == _abi.IAT_EINVAL and "hmax" in msg
+
+
+def test_derivatives_reject_thermal_and_explicit_starts_without_gpu():
+    """Tangent and adjoint differentiate with respect to (theta, phi, E) of a head-on start: thermal
+    batches and caller-given start states are refused before the GPU is touched."""
+    from paper_2509_15117_amd import api
+    L = _abi.load()
+    th = W.fig3_thermal()
+    sysv = api.system_struct(th.system)
+    sp = api.species_array(th.species())
+    o = _obs_dummy()
+    rc = L.iat_integrate_tangent(ctypes.byref(sysv), sp, 5, ctypes.byref(api.batch_struct(4, th.gen)), ctypes.byref(o),
+                                 ctypes.c_void_p(0x1000), None, None, None, None)
+    assert rc == _abi.IAT_ENOTSUP and "thermal" in L.iat_last_error().decode()
+    rc = L.iat_adjoint(ctypes.byref(sysv), sp, 5, ctypes.byref(api.batch_struct(4, th.gen)), ctypes.byref(o),
+                       None, None, None, None, 0, None, None)
+    assert rc == _abi.IAT_ENOTSUP and "thermal" in L.iat_last_error().decode()
+    w = W.config1()
+    b = api.batch_struct(4, W.Generator(kind="arrays"))
+    b.y0 = 0x1000
+    rc = L.iat_integrate_tangent(ctypes.byref(api.system_struct(w.system)), api.species_array(w.species()), 1,
+                                 ctypes.byref(b), ctypes.byref(o), ctypes.c_void_p(0x1000), None, None, None, None)
+    assert rc == _abi.IAT_ENOTSUP and "y0" in L.iat_last_error().decode()
