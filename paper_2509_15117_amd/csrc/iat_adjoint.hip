@@ -381,6 +381,7 @@ __global__ void __launch_bounds__(256) k_adj_reverse(KParams P, Work W, AdjBuf B
     const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 2;     // resident quad
     const int64_t nq = ((int64_t)gridDim.x * blockDim.x) >> 2;
     const int64_t gl = q * 4 + lane4;
+    const StepK K = step_k_in_registers(P);     // latency-bound: launch constants held in registers
     for (int64_t i = q; i < P.n; i += nq) {
         if (B.info[P.n + i] != 1) continue;     // quad-uniform
         Lane L;
@@ -439,7 +440,7 @@ __global__ void __launch_bounds__(256) k_adj_reverse(KParams P, Work W, AdjBuf B
                 sl[5 * B.lanes] = T.F1i;
                 sl[6 * B.lanes] = T.S.tau;
                 double h;
-                const int o = traj4_step(P, T, h);
+                const int o = traj4_step_k(P, K, T, h, kTab);
                 sl[7 * B.lanes] = h;
                 if (o == OUT_ACCEPT) ++c;
                 ++guard;
