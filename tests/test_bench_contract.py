@@ -1,0 +1,44 @@
+"""The benchmark's output contract, checked on the recorded bench lines in profiles/ (no GPU): every
+key the one-line JSON must carry, roofline and CPU-baseline objects included, and the traffic lookup
+that only reports counters taken on the current kernel sources."""
+import json
+import os
+
+import pytest
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+RECORDS = ["bench_yb_rb_grid1024.json", "bench_sweep_5species_225cells.json", "bench_stream_li_k_cs_1e8.json",
+           "bench_fig3_thermal_5species.json", "bench_fig4_energy_sweep_5species.json"]
+
+
+@pytest.mark.parametrize("name", RECORDS)
+def test_recorded_bench_lines_follow_the_contract(name):
+    d = json.load(open(os.path.join(ROOT, "profiles", name)))
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+              "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"):
+        assert k in d, k
+    assert d["n_gpus"] == 1 and d["dtype"] == "f64" and d["data"] == "synthetic" and d["higher_is_better"] is True
+    assert d["vs_baseline"] is None and d["value"] > 0 and "workload" in d["config"]
+    r = d["roofline"]
+    assert r["bound"] == "alu" and r["unit"] == "TFLOP/s" and r["peak"] == bench.FP64_PEAK_TFLOPS
+    assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-12
+    assert "traffic" in r
+    c = d["cpu_baseline"]
+    assert c["kind"] == "oracle" and c["cores"] >= 1 and c["value"] > 0 and c["sample"]
+
+
+def test_traffic_is_reported_only_for_the_sources_it_was_taken_on(tmp_path):
+    tr = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+    tr["sources"] = bench.sources_digest()
+    p = tmp_path / "t.json"
+    p.write_text(json.dumps(tr))
+    wl = tr["workload"]
+    b = bench.traffic_bytes(str(p), wl, "k_integrate_tail")
+    assert b == tr["kernels"]["k_integrate_tail"]["bytes_per_launch"]
+    assert bench.traffic_bytes(str(p), "another_workload", "k_integrate_tail") is None
+    tr["sources"] = "0" * 64
+    p.write_text(json.dumps(tr))
+    assert bench.traffic_bytes(str(p), wl, "k_integrate_tail") is None
+    assert bench.traffic_bytes(str(tmp_path / "missing.json"), wl, "k_integrate_tail") is None
