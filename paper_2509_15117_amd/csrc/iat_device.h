@@ -339,9 +339,15 @@ __device__ __forceinline__ double acc_ion(double inv_mi, double s, double dk, do
 __device__ __forceinline__ Tab tab_in_registers()
 {
     Tab t = kTab;
-    double* v = &t.c2;
-#pragma unroll
-    for (int k = 0; k < (int)(sizeof(Tab) / sizeof(double)); ++k) asm volatile("" : "+v"(v[k]));
+#define IAT_PIN(f) asm volatile("" : "+v"(t.f))
+    IAT_PIN(c2); IAT_PIN(c3); IAT_PIN(c4); IAT_PIN(c5);
+    IAT_PIN(p31); IAT_PIN(p41); IAT_PIN(p42); IAT_PIN(p51); IAT_PIN(p52); IAT_PIN(p53);
+    IAT_PIN(p61); IAT_PIN(p62); IAT_PIN(p63); IAT_PIN(p64);
+    IAT_PIN(q1); IAT_PIN(q2); IAT_PIN(q3); IAT_PIN(q4); IAT_PIN(q5);
+    IAT_PIN(b1); IAT_PIN(b3); IAT_PIN(b4); IAT_PIN(b5); IAT_PIN(b6);
+    IAT_PIN(r1); IAT_PIN(r2); IAT_PIN(r3); IAT_PIN(r4); IAT_PIN(r5); IAT_PIN(r6);
+    IAT_PIN(e1); IAT_PIN(e3); IAT_PIN(e4); IAT_PIN(e5); IAT_PIN(e6); IAT_PIN(e7);
+#undef IAT_PIN
     return t;
 }
 
