@@ -329,6 +329,16 @@ def tangent(problem, theta, phi, E, q_ratio, twin: bool = False):
     return d.reshape(3, 5), Phi.reshape(12, 12), ftle.value
 
 
+def lyapunov_spectrum(Phi, m_atom, m_ion, t_f):
+    """Finite-time Lyapunov spectrum ln sigma_i(D Phi D^-1) / t_f, descending (a.u. time).
+    D = sqrt(mass) on each coordinate of the (r_atom, r_ion, v_atom, v_ion) state: the canonical
+    scaling q = sqrt(m) r, p = sqrt(m) v, in which the stability matrix of the Hamiltonian flow of
+    Eq. (1) is symplectic in the standard form, so its singular values come in pairs s, 1/s."""
+    d = np.sqrt(np.array([m_atom] * 3 + [m_ion] * 3 + [m_atom] * 3 + [m_ion] * 3))
+    Pt = (d[:, None] * np.asarray(Phi)) / d[None, :]
+    return np.log(np.linalg.svd(Pt, compute_uv=False)) / t_f
+
+
 def fd(problem, theta, phi, E, q_ratio, rel_h=1e-6):
     p = np.ascontiguousarray(np.asarray(problem, dtype=PROBLEM).reshape(1))
     qr = np.ascontiguousarray(q_ratio, dtype=np.float64)

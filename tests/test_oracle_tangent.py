@@ -47,6 +47,24 @@ def test_stability_matrix_is_symplectic(gid):
 
 
 @pytest.mark.parametrize("gid", DIRECT_IDS)
+def test_lyapunov_spectrum_comes_in_opposite_pairs(gid):
+    """A symplectic matrix has singular values in pairs (s, 1/s), so the finite-time Lyapunov
+    spectrum of the canonically scaled stability matrix is symmetric: lambda_i + lambda_(13-i) = 0.
+    The Dormand-Prince map is symplectic only up to its truncation error, so on these trajectories
+    (s_max ~ 1e4) the pairs hold to ~3e-5 in ln(s s'), tested at 2e-4; without the sqrt(mass)
+    scaling the pairing fails by more than 1e-2 (the masses differ by a factor two)."""
+    w, p, th, ph = _problem(gid)
+    _, Phi, _ = oracle.tangent(p, th, ph, w.system.E, w.system.q_ratio)
+    t_f = oracle.integrate_one(p)["t_dwell"]
+    lam = oracle.lyapunov_spectrum(Phi, p["m_atom"], p["m_ion"], t_f)
+    assert np.all(np.diff(lam) <= 0) and lam[0] > 0
+    pair = (lam + lam[::-1]) * t_f                      # ln(s_i s_(13-i))
+    assert np.abs(pair).max() < 2e-4, pair
+    s_raw = np.linalg.svd(Phi, compute_uv=False)
+    assert np.abs(np.log(s_raw * s_raw[::-1])).max() > 1e-2
+
+
+@pytest.mark.parametrize("gid", DIRECT_IDS)
 def test_sensitivities_match_central_differences_entrywise(gid):
     """Each sizeable entry (>= 1% of the observable's largest parameter-scaled sensitivity)
     agrees to 1e-3 at the best of several difference steps (the differences themselves resolve
