@@ -225,16 +225,22 @@ int iat_reduce(const iat_system* sys, const iat_species* species, int n_species,
  * obey the same Runge-Kutta scheme with the primal's step sequence).  Per trajectory:
  * dobs_dp[15*n] = d(angle, q_transfer, dE_ion)/d(theta, phi, E, q_x, De), laid out
  * [j*15 + 5*i + p]; ftle[n] = ln(sigma_max(Phi(t_f, 0)))/t_f (per a.u. time), Phi the
- * 12x12 stability matrix of the internal state; Phi_out[144*n] (row-major per
- * trajectory, internal units) or NULL.  Columns that grow past 2^400 are rescaled as they go
+ * 12x12 stability matrix of the internal state; lyap[12*n] or NULL: the finite-time Lyapunov
+ * spectrum ln(sigma_k(D Phi D^-1))/t_f, descending, D = sqrt(mass) on each coordinate (the
+ * canonical scaling in which Phi is symplectic, so the exponents pair as +-lambda up to the
+ * integrator's truncation error); exponents whose sigma_k^2 falls below ~1e-15 sigma_max^2 are
+ * set by rounding (their pairs are the reliable values), and NaN where sigma_k^2 rounds to <= 0;
+ * Phi_out[144*n] (row-major per trajectory, internal units) or NULL.  Columns that grow past
+ * 2^400 are rescaled as they go
  * (exponents tracked per column); Phi_out holds Phi * 2^-e with e the largest column exponent,
  * so e = 0 and Phi_out = Phi unless the stretching passed 2^400 (long-lived complexes), and ftle
- * accounts for e.  Head-on GRID/ARRAYS batches only; y0 batches are rejected (IAT_ENOTSUP).
+ * and lyap account for e.  Head-on GRID/SWEEP/ARRAYS batches only; y0 and THERMAL batches are
+ * rejected (IAT_ENOTSUP).
  * Workspace: one device allocation of n*(22*8 + 5*4 + 14*13*8 + 14*4 [+ 144*8 when Phi_out is
- * NULL and ftle is not]) bytes, stream-ordered on the given stream. */
+ * NULL and ftle or lyap is not]) bytes, stream-ordered on the given stream. */
 int iat_integrate_tangent(const iat_system* sys, const iat_species* species, int n_species,
                           const iat_batch* batch, const iat_obs* obs, double* dobs_dp, double* ftle,
-                          double* Phi_out, const iat_launch* launch, void* stream);
+                          double* lyap, double* Phi_out, const iat_launch* launch, void* stream);
 
 /* Discrete adjoint of the accepted-step map (the sensitivities of the scattering observables of
  * the Fig. 1 caption to the start and model parameters).  Per trajectory j:

@@ -85,7 +85,7 @@ def load():
     L.iat_reduce.argtypes = [_P(System), _P(Species), ctypes.c_int, _P(Batch), _P(Obs), ctypes.c_int, _vp, _vp]
     L.iat_reduce.restype = ctypes.c_int
     L.iat_integrate_tangent.argtypes = [_P(System), _P(Species), ctypes.c_int, _P(Batch), _P(Obs), _vp, _vp,
-                                        _vp, _P(Launch), _vp]
+                                        _vp, _vp, _P(Launch), _vp]
     L.iat_integrate_tangent.restype = ctypes.c_int
     L.iat_adjoint.argtypes = [_P(System), _P(Species), ctypes.c_int, _P(Batch), _P(Obs), _vp, _vp, _vp, _vp,
                               ctypes.c_size_t, _P(Launch), _vp]

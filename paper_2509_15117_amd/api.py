@@ -153,11 +153,13 @@ def integrate_workload(w, n=None, id0=None, **kw):
     return integrate(w.system, w.species(), w.gen, n, id0=id0, **kw)
 
 
-def tangent(system, species, gen, n: int, *, arrays=None, id0=None, phi=False, out=None, stream=None,
+def tangent(system, species, gen, n: int, *, arrays=None, id0=None, phi=False, lyap=False, out=None, stream=None,
             device=None) -> Dict[str, torch.Tensor]:
     """Observables plus their sensitivities d(angle, q_transfer, dE_ion)/d(theta, phi, E, q_x, De)
-    (key 'dobs_dp', shape n x 3 x 5), the finite-time Lyapunov exponent per a.u. time ('ftle')
-    and, with phi=True, the 12 x 12 stability matrix of the internal state ('Phi')."""
+    (key 'dobs_dp', shape n x 3 x 5), the finite-time Lyapunov exponent per a.u. time ('ftle'),
+    with lyap=True the finite-time Lyapunov spectrum of the canonically scaled stability matrix
+    ('lyap', n x 12, descending) and, with phi=True, the 12 x 12 stability matrix of the internal
+    state ('Phi')."""
     L = _abi.load()
     device = device or torch.device("cuda", torch.cuda.current_device())
     if out is None:
@@ -166,13 +168,16 @@ def tangent(system, species, gen, n: int, *, arrays=None, id0=None, phi=False, o
     out["ftle"] = torch.empty(n, dtype=torch.float64, device=device)
     if phi:
         out["Phi"] = torch.empty(n, 12, 12, dtype=torch.float64, device=device)
+    if lyap:
+        out["lyap"] = torch.empty(n, 12, dtype=torch.float64, device=device)
     sysv = system_struct(system)
     sp = species_array(species)
     b = batch_struct(n, gen, arrays, None, id0)
     o = obs_struct(out)
     la = launch_struct()
     rc = L.iat_integrate_tangent(ctypes.byref(sysv), sp, len(species), ctypes.byref(b), ctypes.byref(o),
-                                 _ptr(out["dobs_dp"]), _ptr(out["ftle"]), _ptr(out.get("Phi")), ctypes.byref(la),
+                                 _ptr(out["dobs_dp"]), _ptr(out["ftle"]), _ptr(out.get("lyap")), _ptr(out.get("Phi")),
+                                 ctypes.byref(la),
                                  _stream_handle(stream))
     _abi.check(rc)
     return out

@@ -273,8 +273,9 @@ __global__ void __launch_bounds__(256) k_tangent(KParams P, Work W, TanOut O)
     }
 }
 
-// Largest eigenvalue of a symmetric 12 x 12 matrix by cyclic Jacobi rotations.
-__device__ double sym12_max_eig(double A[144])
+// Eigenvalues of a symmetric 12 x 12 matrix by cyclic Jacobi rotations: on return the diagonal
+// of A holds them.
+__device__ void sym12_jacobi(double A[144])
 {
     for (int sweep = 0; sweep < 30; ++sweep) {
         double off = 0.0, diag = 0.0;
@@ -302,6 +303,10 @@ __device__ double sym12_max_eig(double A[144])
                 }
             }
     }
+}
+__device__ double sym12_max_eig(double A[144])
+{
+    sym12_jacobi(A);
     double mx = A[0];
     for (int p = 1; p < 12; ++p) mx = fmax(mx, A[p * 13]);
     return mx;
@@ -309,7 +314,7 @@ __device__ double sym12_max_eig(double A[144])
 
 // Chain rule to the observables and the FTLE, one thread per trajectory.
 __global__ void __launch_bounds__(128) k_tangent_post(KParams P, Work W, TanOut O, double* dobs, double* ftle,
-                                                      int32_t* phi_exp)
+                                                      double* lyap, int32_t* phi_exp)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P.n) return;
@@ -405,11 +410,11 @@ __global__ void __launch_bounds__(128) k_tangent_post(KParams P, Work W, TanOut 
         out[2 * 5 + pi] = de;
     }
     // FTLE = ln sigma_max(Phi(t_f, 0)) / t_f with Phi from the uncorrected columns
-    if (ftle || phi_exp) {
+    if (ftle || lyap || phi_exp) {
         int emax = E[0];
         for (int c = 1; c < 12; ++c) emax = max(emax, E[c]);
         if (phi_exp) phi_exp[i] = emax;
-        if (ftle) {
+        if (ftle || lyap) {
             double Ph[144], M[144];
             if (O.Phi) {
                 for (int a = 0; a < 144; ++a) Ph[a] = O.Phi[(size_t)i * 144 + a];
@@ -428,9 +433,46 @@ __global__ void __launch_bounds__(128) k_tangent_post(KParams P, Work W, TanOut 
                     for (int m = 0; m < 12; ++m) s += Ph[m * 12 + a] * Ph[m * 12 + b];
                     M[a * 12 + b] = s;
                 }
-            const double lam = sym12_max_eig(M);
             const double t_f = tau / w;
-            ftle[i] = (0.5 * log(lam) - log(sc) + emax * 0.69314718055994530942) / t_f;
+            const double ln2 = 0.69314718055994530942;
+            if (ftle) ftle[i] = (0.5 * log(sym12_max_eig(M)) - log(sc) + emax * ln2) / t_f;
+            if (lyap) {
+                // Lyapunov spectrum of D Phi D^-1, D = sqrt(mass) per coordinate (canonical scaling,
+                // in which Phi is symplectic: the exponents pair as lambda, -lambda)
+                const double ra = sqrt(ma), ri = sqrt(P.m_ion);
+                double dsc[12];
+                for (int k = 0; k < 3; ++k) {
+                    dsc[k] = dsc[6 + k] = ra;
+                    dsc[3 + k] = dsc[9 + k] = ri;
+                }
+                double big2 = 0.0;
+                for (int a = 0; a < 12; ++a)
+                    for (int c = 0; c < 12; ++c) {
+                        Ph[a * 12 + c] *= dsc[a] / dsc[c];
+                        big2 = fmax(big2, fabs(Ph[a * 12 + c]));
+                    }
+                const double sc2 = big2 > 0.0 ? 1.0 / big2 : 1.0;
+                for (int a = 0; a < 144; ++a) Ph[a] *= sc2;
+                for (int a = 0; a < 12; ++a)
+                    for (int b = 0; b < 12; ++b) {
+                        double s = 0.0;
+                        for (int m = 0; m < 12; ++m) s += Ph[m * 12 + a] * Ph[m * 12 + b];
+                        M[a * 12 + b] = s;
+                    }
+                sym12_jacobi(M);
+                double ev[12];
+                for (int a = 0; a < 12; ++a) ev[a] = M[a * 13];
+                for (int a = 1; a < 12; ++a)          // descending
+                    for (int b = a; b > 0 && ev[b] > ev[b - 1]; --b) {
+                        const double t = ev[b];
+                        ev[b] = ev[b - 1];
+                        ev[b - 1] = t;
+                    }
+                for (int a = 0; a < 12; ++a)
+                    lyap[(size_t)i * 12 + a] = ev[a] > 0.0
+                        ? (0.5 * log(ev[a]) - log(sc) - log(sc2) + emax * ln2) / t_f
+                        : __builtin_nan("");
+            }
         }
     }
     if (O.Phi) {
@@ -449,7 +491,7 @@ using namespace iat;
 
 extern "C" int iat_integrate_tangent(const iat_system* sys, const iat_species* species, int n_species,
                                      const iat_batch* batch, const iat_obs* obs, double* dobs_dp, double* ftle,
-                                     double* Phi_out, const iat_launch* launch, void* stream)
+                                     double* lyap, double* Phi_out, const iat_launch* launch, void* stream)
 {
     int rc = validate_common(sys, species, n_species, batch);
     if (rc) return rc;
@@ -472,7 +514,7 @@ extern "C" int iat_integrate_tangent(const iat_system* sys, const iat_species* s
     const size_t ex_bytes = (size_t)n * kCols * sizeof(int32_t);
     const size_t phi_bytes = (size_t)n * 144 * sizeof(double);
     auto up = [](size_t b) { return (b + 255) / 256 * 256; };
-    const bool own_phi = Phi_out == nullptr && ftle != nullptr;
+    const bool own_phi = Phi_out == nullptr && (ftle != nullptr || lyap != nullptr);
     const size_t bytes = up(work_bytes) + up(col_bytes) + up(ex_bytes) + (own_phi ? up(phi_bytes) : 0);
     void* ws = nullptr;
     if (hipMallocAsync(&ws, bytes, st) != hipSuccess) return set_error(IAT_EHIP, "hipMallocAsync of %zu bytes failed", bytes);
@@ -489,7 +531,7 @@ extern "C" int iat_integrate_tangent(const iat_system* sys, const iat_species* s
     const int64_t lanes = n * 64;
     hipLaunchKernelGGL(k_tangent, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, st, P, W, O);
     hipLaunchKernelGGL(k_tangent_post, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, P, W, O, dobs_dp, ftle,
-                       (int32_t*)nullptr);
+                       lyap, (int32_t*)nullptr);
     launch_observe(P, W, st);
     if (hipFreeAsync(ws, st) != hipSuccess) return set_error(IAT_EHIP, "hipFreeAsync failed");
     hipError_t e = hipGetLastError();

@@ -110,7 +110,7 @@ def test_derivatives_reject_thermal_and_explicit_starts_without_gpu():
     sp = api.species_array(th.species())
     o = _obs_dummy()
     rc = L.iat_integrate_tangent(ctypes.byref(sysv), sp, 5, ctypes.byref(api.batch_struct(4, th.gen)), ctypes.byref(o),
-                                 ctypes.c_void_p(0x1000), None, None, None, None)
+                                 ctypes.c_void_p(0x1000), None, None, None, None, None)
     assert rc == _abi.IAT_ENOTSUP and "thermal" in L.iat_last_error().decode()
     rc = L.iat_adjoint(ctypes.byref(sysv), sp, 5, ctypes.byref(api.batch_struct(4, th.gen)), ctypes.byref(o),
                        None, None, None, None, 0, None, None)
@@ -119,5 +119,5 @@ def test_derivatives_reject_thermal_and_explicit_starts_without_gpu():
     b = api.batch_struct(4, W.Generator(kind="arrays"))
     b.y0 = 0x1000
     rc = L.iat_integrate_tangent(ctypes.byref(api.system_struct(w.system)), api.species_array(w.species()), 1,
-                                 ctypes.byref(b), ctypes.byref(o), ctypes.c_void_p(0x1000), None, None, None, None)
+                                 ctypes.byref(b), ctypes.byref(o), ctypes.c_void_p(0x1000), None, None, None, None, None)
     assert rc == _abi.IAT_ENOTSUP and "y0" in L.iat_last_error().decode()

@@ -85,3 +85,47 @@ def test_stability_matrix_symplectic_and_ftle_consistent():
         smax = np.linalg.svd(Phi, compute_uv=False)[0]
         assert abs(out["ftle"][gid] - np.log(smax) / out["t_dwell"][gid]) <= 1e-10 * abs(out["ftle"][gid])
     assert np.all(np.isfinite(out["ftle"])) and np.all(out["ftle"] > 0)
+
+
+def test_lyapunov_spectrum_matches_oracle_and_pairs():
+    """The finite-time Lyapunov spectrum of the canonically scaled stability matrix: per direct
+    trajectory of the 8x8 grid, every exponent whose singular value is resolvable (s_k^2 above
+    1e-12 s_max^2) equals the oracle's (numpy SVD of the oracle's Phi) in ln s_k within
+    max(12e-9 s_max / s_k, 10 x the spread of the oracle's five round-off probes): the first term is
+    the Phi test's entrywise bar (1e-9 max|Phi|) carried to s_k by Weyl's inequality
+    (|d s_k| <= ||d Phi||_2 <= 12 max|d Phi_ij|).  Pairs whose smaller member is resolvable sum to
+    zero within 2e-4 in ln(s s') (the Dormand-Prince map is symplectic up to its truncation error);
+    below s_max * 1e-6 the normal matrix the library diagonalises holds the small singular values
+    only to rounding, and their pairs are the reliable values."""
+    w = W.config1()
+    out = PT.to_numpy(api.tangent(w.system, w.species(), w.gen, 64, lyap=True))
+    P = oracle.problems_for(w, range(64))
+    ref = oracle.integrate(P)
+    th_ph = oracle.grid_angles(range(64), 8, 8)
+    m_a, m_i = P[0]["m_atom"], P[0]["m_ion"]
+    for gid in DIRECT:
+        t_f = ref[gid]["t_dwell"]
+        lam = out["lyap"][gid]
+        assert np.all(np.isfinite(lam)) and np.all(np.diff(lam) <= 0)
+        _, Phi, _, _ = tangent_spread(P[gid], th_ph[gid][0], th_ph[gid][1], w)
+        lo = oracle.lyapunov_spectrum(Phi, m_a, m_i, t_f)
+        # the probes' spread of the oracle's spectrum, in ln s
+        spread = np.zeros(12)
+        q_runs = [oracle.tangent(P[gid], th_ph[gid][0], th_ph[gid][1], w.system.E, w.system.q_ratio, twin=True)]
+        for sg in PT.PROBE_SIGNS:
+            q = P[gid].copy()
+            q["y0"][0:3] *= 1.0 + sg * 2.0 ** -52
+            q_runs.append(oracle.tangent(q, th_ph[gid][0], th_ph[gid][1], w.system.E, w.system.q_ratio))
+        for _, P2, _ in q_runs:
+            spread = np.maximum(spread, np.abs(oracle.lyapunov_spectrum(P2, m_a, m_i, t_f) - lo) * t_f)
+        ok = (lo - lo[0]) * t_f > 0.5 * np.log(1e-12)
+        err = np.abs(lam - lo) * t_f
+        bar = np.maximum(12e-9 * np.exp((lo[0] - lo) * t_f), 10.0 * spread)
+        print(f"id {gid}: s_max {np.exp(lo[0] * t_f):.2e}, worst |ln s_gpu - ln s_oracle| {err[ok].max():.1e} "
+              f"(bar {bar[ok].min():.1e}..{bar[ok].max():.1e}), resolvable pairs "
+              f"{np.abs((lam + lam[::-1]) * t_f)[ok & ok[::-1]].max():.1e}",
+              flush=True)
+        assert np.all(err[ok] <= bar[ok]), (gid, err, bar)
+        # pairs whose smaller member is resolvable through the normal matrix (s^2 above 1e-12 s_max^2)
+        both = ok & ok[::-1]
+        assert both.sum() >= 6 and np.abs((lam + lam[::-1]) * t_f)[both].max() < 2e-4
