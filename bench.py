@@ -152,9 +152,9 @@ def chunked_job(api, torch, w, n, args, stats, kernel):
 def kernel_profile(api, torch, w, n, kernel):
     """Event-timed phases of one single-stream call on ids [0, n): the per-kernel roofline figures."""
     import ctypes
-    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    stats = api.new_stats()
     out = api.alloc_obs(n, torch.device("cuda", 0), counters=False)
-    ms = (ctypes.c_float * 4)()
+    ms = api.phase_ms()
     api.integrate_workload(w, n=n, out=out, stats=stats, kernel_ms=ms, kernel=kernel)
     s = stats.cpu().tolist()
     return list(ms), s
@@ -166,7 +166,7 @@ def main_chunked(args):
     torch.cuda.set_device(0)
     w = workload(args.workload)
     n = args.n or w.n
-    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    stats = api.new_stats()
     for _ in range(args.warmup):
         chunked_job(api, torch, w, n, args, None, args.kernel)
     secs, res = 0.0, None
@@ -185,7 +185,8 @@ def main_chunked(args):
     print(f"[bench] phases ms {[round(x, 1) for x in ms]}", file=sys.stderr, flush=True)
     main_name = "k_integrate_persistent" if args.kernel == "persistent" else "k_integrate_plain"
     kernels = []
-    for name, secs_k, rhs in ((main_name, ms[1] / 1e3, ks[0] - ks[6]), ("k_integrate_tail", ms[2] / 1e3, ks[6])):
+    for name, secs_k, rhs in ((main_name, ms[1] / 1e3, ks[0] - ks[6] - ks[8]), ("k_integrate_tail", ms[2] / 1e3, ks[6]),
+                              ("k_integrate_solo", ms[3] / 1e3, ks[8])):
         if secs_k > 0:
             tf = FLOP_PER_RHS * rhs / secs_k / 1e12
             kernels.append({"kernel": name, "avg_launch_ms": secs_k * 1e3, "rhs_per_launch": rhs,
@@ -256,10 +257,11 @@ def pipelined(api, torch, w, passes, launch):
 
 
 def critical_path(api, torch, w, tail_ms, budget=20000, cap=400_000):
-    """The tail kernel is latency-bound: it cannot end before the longest trajectory has run its
-    steps beyond the budget, one after another, at the per-step latency of a trajectory alone in the
-    four-lane form.  One more pass with step counters finds that trajectory; a bounded prefix of it
-    (`cap` accepted steps) timed alone gives the latency.  frac = that bound / the tail's duration."""
+    """The tail phase (four-lane tail kernel, then the solo kernel) is latency-bound: it cannot end
+    before the longest trajectory has run its steps beyond the budget, one after another, at the
+    per-step latency of a trajectory alone in its wave.  One more pass with step counters finds that
+    trajectory; a bounded prefix of it (`cap` accepted steps) timed alone in the solo kernel gives the
+    latency.  frac = that bound / the tail phase's duration."""
     import copy
     import ctypes
     o = api.integrate_workload(w, counters=True)
@@ -268,10 +270,12 @@ def critical_path(api, torch, w, tail_ms, budget=20000, cap=400_000):
     n_steps = int(steps[i].item())
     wl = copy.deepcopy(w)
     wl.system.max_steps = cap
-    ms = (ctypes.c_float * 4)()
-    r = api.integrate_workload(wl, n=1, id0=i, counters=True, kernel="persistent", step_budget=1, kernel_ms=ms)
-    s1 = int(r["n_accept"].item() + r["n_reject"].item())
-    us = ms[2] * 1e3 / max(s1, 1)
+    ms = api.phase_ms()
+    # one attempted step in the main kernel, one in the four-lane tail, the rest in the solo kernel
+    r = api.integrate_workload(wl, n=1, id0=i, counters=True, kernel="persistent", step_budget=1, tail_budget=1,
+                               kernel_ms=ms)
+    s1 = int(r["n_accept"].item() + r["n_reject"].item()) - 2
+    us = ms[3] * 1e3 / max(s1, 1)
     bound_ms = max(n_steps - budget, 0) * us / 1e3
     print(f"[bench] longest trajectory {i}: {n_steps} attempted steps, {us:.3f} us per step alone", file=sys.stderr,
           flush=True)
@@ -296,7 +300,7 @@ def timed_runs(api, torch, w, out, stats, steps, warmup, **launch):
     t0 = time.perf_counter()
     ev0.record(stream)
     for k in range(steps):
-        ms = (ctypes.c_float * 4)()
+        ms = api.phase_ms()
         api.integrate_workload(w, out=out, stats=stats, kernel_ms=ms, **launch)
         phases.append(list(ms))
         print(f"[bench] pass {k + 1}/{steps} ({launch.get('kernel')}): phases ms "
@@ -306,9 +310,9 @@ def timed_runs(api, torch, w, out, stats, steps, warmup, **launch):
     wall = time.perf_counter() - t0
     total_ms = ev0.elapsed_time(ev1)
     s = stats.cpu().tolist()
-    avg = [sum(p[j] for p in phases) / len(phases) for j in range(4)]
+    avg = [sum(p[j] for p in phases) / len(phases) for j in range(len(phases[0]))]
     return dict(total_s=total_ms / 1e3, wall_s=wall, phase_ms=avg, rhs=s[0], acc=s[1], rej=s[2],
-                done=s[3], issued=s[4], useful=s[5], tail_rhs=s[6], tail_done=s[7])
+                done=s[3], issued=s[4], useful=s[5], tail_rhs=s[6], tail_done=s[7], solo_rhs=s[8], solo_done=s[9])
 
 
 def cpu_baseline(w, target_s):
@@ -385,12 +389,13 @@ def lone_latency(args):
         w.system.max_steps = args.max_steps
     api.integrate_workload(w, n=64)          # warm-up
     res = {"workload": w.name, "id": args.latency}
-    for form, budget in (("four_lane_tail", 1), ("one_lane", -1)):
-        ms = (ctypes.c_float * 4)()
+    # (step budget, tail budget, phase): the solo kernel, the four-lane tail kernel, the one-lane kernel
+    for form, budget, budget2, ph in (("solo", 1, 1, 3), ("four_lane_tail", 1, -1, 2), ("one_lane", -1, 0, 1)):
+        ms = api.phase_ms()
         o = api.integrate_workload(w, n=1, id0=args.latency, counters=True, kernel="persistent", step_budget=budget,
-                                   kernel_ms=ms)
-        steps = int(o["n_accept"].item() + o["n_reject"].item())
-        t = ms[2] if budget == 1 else ms[1]
+                                   tail_budget=budget2, kernel_ms=ms)
+        steps = int(o["n_accept"].item() + o["n_reject"].item()) - (ph - 1)
+        t = ms[ph]
         res[form] = {"attempted_steps": steps, "ms": t, "us_per_step": t * 1e3 / max(steps, 1),
                      "status": int(o["status"].item())}
     print(json.dumps(res), flush=True)
@@ -427,7 +432,7 @@ def main():
     torch.cuda.set_device(0)
     w = workload(args.workload)
     out = api.alloc_obs(w.n, torch.device("cuda", 0), counters=False)
-    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    stats = api.new_stats()
     launch = dict(kernel=args.kernel, block=args.block, blocks_per_cu=args.blocks_per_cu,
                   refill_every=args.refill_every)
     if args.autotune and args.kernel == "persistent":
@@ -442,8 +447,9 @@ def main():
     # own; the main kernel did the rest), over its event-timed average launch duration
     main_name = "k_integrate_persistent" if args.kernel == "persistent" else "k_integrate_plain"
     kernels = []
-    for name, secs, rhs in ((main_name, r["phase_ms"][1] / 1e3, (r["rhs"] - r["tail_rhs"]) / K),
-                            ("k_integrate_tail", r["phase_ms"][2] / 1e3, r["tail_rhs"] / K)):
+    for name, secs, rhs in ((main_name, r["phase_ms"][1] / 1e3, (r["rhs"] - r["tail_rhs"] - r["solo_rhs"]) / K),
+                            ("k_integrate_tail", r["phase_ms"][2] / 1e3, r["tail_rhs"] / K),
+                            ("k_integrate_solo", r["phase_ms"][3] / 1e3, r["solo_rhs"] / K)):
         if secs <= 0.0:
             continue
         tflops = FLOP_PER_RHS * rhs / secs / 1e12
@@ -476,8 +482,9 @@ def main():
                      "avg_launch_ms": dom["avg_launch_ms"], "flop_per_launch": dom["flop_per_launch"]},
         "kernels": kernels,
         "phases_ms": {"setup": r["phase_ms"][0], "main": r["phase_ms"][1], "tail": r["phase_ms"][2],
-                      "observe": r["phase_ms"][3]},
-        "tail_trajectories": r["tail_done"] / K,
+                      "solo": r["phase_ms"][3], "observe": r["phase_ms"][4]},
+        "tail_trajectories": (r["tail_done"] + r["solo_done"]) / K,
+        "solo_trajectories": r["solo_done"] / K,
     }
     if not args.no_plain and args.kernel != "plain":
         rp = timed_runs(api, torch, w, out, stats, 1, 0, **dict(launch, kernel="plain"))
@@ -486,7 +493,7 @@ def main():
                         "active_lane_fraction": rp["useful"] / max(rp["issued"], 1), "ms": rp["total_s"] * 1e3}
         res["speedup_vs_plain"] = traj_s / res["plain"]["trajectories_per_s"]
     if args.kernel == "persistent" and not args.no_critical_path:
-        res["critical_path"] = critical_path(api, torch, w, r["phase_ms"][2])
+        res["critical_path"] = critical_path(api, torch, w, r["phase_ms"][2] + r["phase_ms"][3])
     if args.inflight > 1:
         res["pipelined"] = pipelined(api, torch, w, args.inflight, launch)
     pk = api.fp64_peak()

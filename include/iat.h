@@ -157,16 +157,19 @@ enum { IAT_KERNEL_PLAIN = 1, IAT_KERNEL_PERSISTENT = 2 };
 
 /* Launch shape.  kernel: PLAIN = one lane per trajectory, one launch per batch;
  * PERSISTENT = resident grid whose lanes refill from a device work queue; trajectories that
- * outlive step_budget continue four lanes per trajectory in a second kernel.  Both kernels
- * give the same bits for the same trajectory.
- * Zero fields take defaults.  stats, if not NULL, is a device uint64[8] to which the
+ * outlive step_budget continue four lanes per trajectory in a second kernel, and those that
+ * outlive tail_budget there finish in a third, one trajectory per wave.  All kernels give the
+ * same bits for the same trajectory.
+ * Zero fields take defaults.  stats, if not NULL, is a device uint64[10] to which the
  * call ADDS: [0] RHS evaluations, [1] accepted steps, [2] rejected steps,
- * [3] trajectories finished, [4] issued lane-steps (wave iterations x 64),
- * [5] useful lane-steps (attempted steps), [6] RHS evaluations performed inside the
- * four-lane tail kernel, [7] trajectories finished by the tail kernel.
- * kernel_ms, if not NULL, is HOST float[4] that receives the durations of the call's phases on
- * its stream (setup, main integration kernel, tail kernel, observables), measured with HIP
- * events; the call then waits for its work to finish before returning. */
+ * [3] trajectories finished, [4] issued step slots (one-lane kernels: wave iterations x 64;
+ * four-lane kernels: wave iterations x trajectories per wave), [5] useful step slots (attempted
+ * steps), [6] RHS evaluations performed inside the four-lane tail kernel, [7] trajectories
+ * finished by it, [8] RHS evaluations performed inside the one-per-wave solo kernel,
+ * [9] trajectories finished by it.
+ * kernel_ms, if not NULL, is HOST float[5] that receives the durations of the call's phases on
+ * its stream (setup, main integration kernel, four-lane tail kernel, solo kernel, observables),
+ * measured with HIP events; the call then waits for its work to finish before returning. */
 typedef struct {
     int32_t kernel;
     int32_t block;            /* threads per block: 64, 128, 192 or 256                */
@@ -180,6 +183,11 @@ typedef struct {
                                  one call (continuation records of 248 B each, allocated
                                  with the call's workspace); the others finish in the
                                  one-lane kernel.  0 = min(n, 2^23)                      */
+    int32_t tail_budget;      /* PERSISTENT: attempted steps in the four-lane tail after which
+                                 a trajectory is suspended again and finished alone in its
+                                 wave (at most min(max_suspended, 2^16) of them per call; the
+                                 others stay in the tail); 0 = default (50000), -1 = never */
+    int32_t reserved;         /* must be 0                                                */
     uint64_t* stats;
     float* kernel_ms;
 } iat_launch;

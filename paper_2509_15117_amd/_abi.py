@@ -12,6 +12,7 @@ ST_COMPLEX, ST_BOUND_SEEN, ST_EXITED = 1 << 0, 1 << 1, 1 << 2
 ST_TMAX, ST_H_UNDERFLOW, ST_NONFINITE, ST_MAX_STEPS = 1 << 8, 1 << 9, 1 << 10, 1 << 11
 ST_R_UNDERFLOW, ST_WARN_R0, ST_ADJ_SKIPPED = 1 << 12, 1 << 13, 1 << 14
 MAX_SPECIES = 8
+N_STATS, N_PHASES = 10, 5
 GEN_ARRAYS, GEN_GRID, GEN_SWEEP, GEN_THERMAL = 0, 1, 2, 3
 KERNEL_PLAIN, KERNEL_PERSISTENT = 1, 2
 REDUCE_CELLS, REDUCE_W0_HIST, REDUCE_BOXCOUNT, REDUCE_LIFETIME = 1, 2, 3, 4
@@ -59,7 +60,8 @@ class Obs(ctypes.Structure):
 class Launch(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("refill_every", ctypes.c_int32), ("step_budget", ctypes.c_int32),
-                ("max_suspended", ctypes.c_int32), ("stats", _vp), ("kernel_ms", _vp)]
+                ("max_suspended", ctypes.c_int32), ("tail_budget", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("stats", _vp), ("kernel_ms", _vp)]
 
 
 _P = ctypes.POINTER

@@ -111,26 +111,45 @@ def batch_struct(n: int, gen, arrays: Optional[Dict[str, torch.Tensor]] = None,
 
 
 def launch_struct(kernel="persistent", block=0, blocks_per_cu=0, refill_every=0, step_budget=0,
-                  stats: Optional[torch.Tensor] = None, kernel_ms=None, max_suspended=0) -> _abi.Launch:
-    """kernel_ms: optional host ctypes float[4] for the phase durations (the call then waits)."""
+                  stats: Optional[torch.Tensor] = None, kernel_ms=None, max_suspended=0,
+                  tail_budget=0) -> _abi.Launch:
+    """stats: optional device int64 tensor of at least 10 counters; kernel_ms: optional host
+    ctypes float[5] for the phase durations (the call then waits).  Both are checked for size here,
+    since the library writes all of their entries."""
+    if stats is not None and (stats.numel() < _abi.N_STATS or stats.dtype != torch.int64 or not stats.is_cuda
+                              or not stats.is_contiguous()):
+        raise ValueError(f"stats must be a contiguous device int64 tensor of >= {_abi.N_STATS} entries")
+    if kernel_ms is not None and len(kernel_ms) < _abi.N_PHASES:
+        raise ValueError(f"kernel_ms must hold >= {_abi.N_PHASES} floats")
     L = _abi.Launch()
     L.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     L.block, L.blocks_per_cu, L.refill_every = block, blocks_per_cu, refill_every
     L.step_budget = step_budget
     L.max_suspended = max_suspended
+    L.tail_budget = tail_budget
     L.stats = _ptr(stats)
     L.kernel_ms = None if kernel_ms is None else ctypes.cast(kernel_ms, ctypes.c_void_p)
     return L
 
 
+def phase_ms():
+    """A host buffer for the phase durations of one call: setup, main, tail, solo, observables."""
+    return (ctypes.c_float * _abi.N_PHASES)()
+
+
+def new_stats(device=None) -> torch.Tensor:
+    """Zeroed device counters for launch.stats (see include/iat.h for the entries)."""
+    return torch.zeros(_abi.N_STATS, dtype=torch.int64, device=device or "cuda")
+
+
 def integrate(system, species, gen, n: int, *, arrays=None, y0=None, id0=None, kernel="persistent", block=0,
               blocks_per_cu=0, refill_every=0, step_budget=0, y_final=False, counters=True, stats=None, out=None,
-              stream=None, device=None, kernel_ms=None, max_suspended=0) -> Dict[str, torch.Tensor]:
+              stream=None, device=None, kernel_ms=None, max_suspended=0, tail_budget=0) -> Dict[str, torch.Tensor]:
     """Integrate n trajectories on the current GPU; returns device tensors of the observables.
 
     system / gen: objects with the fields of workloads.System / workloads.Generator.
-    species: [(m_atom, C4)] in atomic units.  stats: optional uint64[8] device counters (int64 tensor).
-    kernel_ms: optional (ctypes.c_float * 4)() receiving the phase durations (setup, main, tail,
+    species: [(m_atom, C4)] in atomic units.  stats: optional uint64[10] device counters (new_stats()).
+    kernel_ms: optional phase_ms() buffer receiving the phase durations (setup, main, tail, solo,
     observables) measured with HIP events on the stream; the call then waits for completion."""
     L = _abi.load()
     device = device or torch.device("cuda", torch.cuda.current_device())
@@ -140,7 +159,8 @@ def integrate(system, species, gen, n: int, *, arrays=None, y0=None, id0=None, k
     sp = species_array(species)
     b = batch_struct(n, gen, arrays, y0, id0)
     o = obs_struct(out)
-    la = launch_struct(kernel, block, blocks_per_cu, refill_every, step_budget, stats, kernel_ms, max_suspended)
+    la = launch_struct(kernel, block, blocks_per_cu, refill_every, step_budget, stats, kernel_ms, max_suspended,
+                       tail_budget)
     rc = L.iat_integrate(ctypes.byref(sysv), sp, len(species), ctypes.byref(b), ctypes.byref(o), ctypes.byref(la),
                          None, 0, _stream_handle(stream))
     _abi.check(rc)

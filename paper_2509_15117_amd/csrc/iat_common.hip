@@ -204,7 +204,7 @@ void fill_outputs(KParams& P, const iat_obs* obs)
 PhaseTimer::PhaseTimer(float* out, hipStream_t st) : out_(out), st_(st)
 {
     if (!out_) return;
-    for (int k = 0; k < 5; ++k)
+    for (int k = 0; k < kMarks; ++k)
         if (hipEventCreate(&ev_[k]) != hipSuccess) ev_[k] = nullptr;
 }
 void PhaseTimer::mark(int k)
@@ -215,8 +215,9 @@ int PhaseTimer::finish()
 {
     if (!out_) return 0;
     int rc = 0;
-    if (hipEventSynchronize(ev_[4]) != hipSuccess) rc = set_error(IAT_EHIP, "timing: hipEventSynchronize failed");
-    for (int k = 0; k < 4 && rc == 0; ++k)
+    if (hipEventSynchronize(ev_[kMarks - 1]) != hipSuccess)
+        rc = set_error(IAT_EHIP, "timing: hipEventSynchronize failed");
+    for (int k = 0; k + 1 < kMarks && rc == 0; ++k)
         if (hipEventElapsedTime(&out_[k], ev_[k], ev_[k + 1]) != hipSuccess)
             rc = set_error(IAT_EHIP, "timing: hipEventElapsedTime failed");
     return rc;
@@ -224,7 +225,7 @@ int PhaseTimer::finish()
 PhaseTimer::~PhaseTimer()
 {
     if (!out_) return;
-    for (int k = 0; k < 5; ++k)
+    for (int k = 0; k < kMarks; ++k)
         if (ev_[k]) (void)hipEventDestroy(ev_[k]);
 }
 
@@ -244,6 +245,8 @@ int resolve_launch(const iat_launch* launch, iat_launch* out)
         return set_error(IAT_EINVAL, "launch.refill_every must be in [1, 4096]");
     if (L.step_budget < -1) return set_error(IAT_EINVAL, "launch.step_budget must be >= -1");
     if (L.max_suspended < 0) return set_error(IAT_EINVAL, "launch.max_suspended must be >= 0");
+    if (L.tail_budget < -1) return set_error(IAT_EINVAL, "launch.tail_budget must be >= -1");
+    if (L.reserved != 0) return set_error(IAT_EINVAL, "launch.reserved must be 0");
     *out = L;
     return 0;
 }

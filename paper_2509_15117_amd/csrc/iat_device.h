@@ -1256,6 +1256,40 @@ __device__ inline void cont_load4(const KParams& P, const Work& W, const Cont& C
     work_lane(W, i, T.L);
 }
 
+// The record of a four-lane trajectory (the layout of cont_save): lanes 0..2 of the quad write
+// their axis, lane 0 the scalar state and the id.
+__device__ inline void cont_save4(const Cont& C, int64_t slot, int64_t i, const Traj4& T, int lane_in_quad)
+{
+    const int64_t c = C.cap;
+    if (lane_in_quad < 3) {
+        const int k = lane_in_quad;
+        C.d[(0 + k) * c + slot] = T.xa;
+        C.d[(3 + k) * c + slot] = T.xi;
+        C.d[(6 + k) * c + slot] = T.va;
+        C.d[(9 + k) * c + slot] = T.vi;
+        C.d[(12 + k) * c + slot] = T.F1a;
+        C.d[(15 + k) * c + slot] = T.F1i;
+    }
+    if (lane_in_quad != 0) return;
+    const Scal& S = T.S;
+    C.d[18 * c + slot] = S.tau;
+    C.d[19 * c + slot] = S.h;
+    C.d[20 * c + slot] = S.rho_prev;
+    C.d[21 * c + slot] = S.s_prev;
+    C.d[22 * c + slot] = S.sx1;
+    C.d[23 * c + slot] = S.sg1;
+    C.d[24 * c + slot] = S.tau_first;
+    C.d[25 * c + slot] = S.tau_last;
+    C.n[0 * c + slot] = S.nacc;
+    C.n[1 * c + slot] = S.nrej;
+    C.n[2 * c + slot] = S.nrhs;
+    C.n[3 * c + slot] = S.nb;
+    C.n[4 * c + slot] = (int32_t)S.status;
+    C.n[5 * c + slot] = (int32_t)S.mode;
+    C.n[6 * c + slot] = S.last_rej;
+    C.id[slot] = i;
+}
+
 __device__ __forceinline__ void traj4_store(const Work& W, int64_t i, const Traj4& T, int lane_in_quad)
 {
     if (lane_in_quad < 3) {

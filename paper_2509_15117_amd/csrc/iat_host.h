@@ -19,17 +19,19 @@ int resolve_launch(const iat_launch* launch, iat_launch* out);
 void launch_setup(const KParams& P, const Work& W, hipStream_t st);
 void launch_observe(const KParams& P, const Work& W, hipStream_t st);
 
-// HIP-event timing of a call's phases into a host float[4] (no-op when out is NULL).
+// HIP-event timing of a call's phases into a host float[kMarks - 1] (no-op when out is NULL).
 class PhaseTimer {
 public:
+    static constexpr int kMarks = 6;
     PhaseTimer(float* out, hipStream_t st);
     ~PhaseTimer();
-    void mark(int k);      // k = 0..4: before setup, after setup, after main, after tail, after observe
+    // k = 0..5: before setup, after setup, after main, after tail, after solo, after observe
+    void mark(int k);
     int finish();          // waits for the last mark; 0 or an error code
 private:
     float* out_;
     hipStream_t st_;
-    hipEvent_t ev_[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev_[kMarks] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
 }  // namespace iat

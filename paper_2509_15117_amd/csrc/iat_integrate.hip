@@ -23,6 +23,8 @@ namespace iat {
 
 constexpr int64_t kDefaultBudget = 20000;        // attempted steps before a trajectory moves to 4 lanes
 constexpr int64_t kMaxSuspended = 1 << 23;       // continuation records per call (248 B each)
+constexpr int64_t kDefaultTailBudget = 50000;   // attempted steps in the four-lane tail before the solo level
+constexpr int64_t kMaxSolo = 1 << 16;            // records of the solo level per call
 
 __device__ __forceinline__ uint64_t wave_sum(uint64_t v)
 {
@@ -155,9 +157,14 @@ __global__ void __launch_bounds__(256) k_integrate_persistent(KParams P, Work W,
 }
 
 // Finishes suspended trajectories with four lanes each (one per axis): the per-step latency of
-// a long-lived complex is what bounds a batch's wall time.
-template <bool CE>
-__global__ void __launch_bounds__(256) k_integrate_tail(KParams P, Work W, Cont C)
+// a long-lived complex is what bounds a batch's wall time.  QUADS trajectories share a wave.
+// With budget2 > 0, a trajectory that has run budget2 more attempted steps here is suspended
+// again into C2 (while its slots last) and its quad takes new work; k_integrate_solo finishes
+// those one per wave, so the longest complexes run without wave or SIMD neighbours.  Counters:
+// stats[si] RHS evaluations and stats[si + 1] trajectories finished in this kernel.
+template <bool CE, int QUADS>
+__device__ __forceinline__ void tail_run(const KParams& P, const Work& W, const Cont& C, const Cont& C2,
+                                         int budget2, int si)
 {
     const int lane = __lane_id();
     const int qlead = lane & ~3;
@@ -172,7 +179,7 @@ __global__ void __launch_bounds__(256) k_integrate_tail(KParams P, Work W, Cont 
     int64_t i = -1;
     int32_t resumed_at = 0, resumed_rhs = 0;
     uint64_t tail_rhs = 0, tail_done = 0;
-    bool active = false, need = true;
+    bool active = false, need = (lane >> 2) < QUADS, may_suspend = budget2 > 0 && C2.cap > 0;
     const Tab B = tab_in_registers();
     const StepK K = step_k_in_registers(P);
     for (;;) {
@@ -208,19 +215,47 @@ __global__ void __launch_bounds__(256) k_integrate_tail(KParams P, Work W, Cont 
                 tail_done += 1;
             }
             active = false;
-            need = true;
+            need = (lane >> 2) < QUADS;
+        } else if (active && may_suspend && T.S.nacc + T.S.nrej - resumed_at >= budget2) {
+            // quad-uniform: the whole quad holds the same scalar state
+            unsigned long long s2 = 0;
+            if (leader) s2 = atomicAdd(C2.count, 1ull);
+            s2 = __shfl(s2, qlead, 64);
+            if ((int64_t)s2 < C2.cap) {
+                cont_save4(C2, (int64_t)s2, i, T, lane & 3);
+                if (leader) {
+                    st.useful += T.S.nacc + T.S.nrej - resumed_at;
+                    tail_rhs += (uint64_t)(T.S.nrhs - resumed_rhs);
+                }
+                active = false;
+                need = true;
+            } else {
+                may_suspend = false;
+            }
         }
     }
-    // a wave carries 16 trajectories: 16 step slots per iteration
     flush_stats(P.stats, st, 0ull);
     if (P.stats) {
         const uint64_t tr = wave_sum(tail_rhs), td = wave_sum(tail_done);
         if (lane == 0) {
-            atomicAdd((unsigned long long*)&P.stats[4], (unsigned long long)(16ull * iters));
-            atomicAdd((unsigned long long*)&P.stats[6], (unsigned long long)tr);
-            atomicAdd((unsigned long long*)&P.stats[7], (unsigned long long)td);
+            atomicAdd((unsigned long long*)&P.stats[4], (unsigned long long)QUADS * iters);
+            atomicAdd((unsigned long long*)&P.stats[si], (unsigned long long)tr);
+            atomicAdd((unsigned long long*)&P.stats[si + 1], (unsigned long long)td);
         }
     }
+}
+
+template <bool CE>
+__global__ void __launch_bounds__(256) k_integrate_tail(KParams P, Work W, Cont C, Cont C2, int budget2)
+{
+    tail_run<CE, 16>(P, W, C, C2, budget2, 6);
+}
+
+// One trajectory (one quad) per wave, launched one wave per block.
+template <bool CE>
+__global__ void __launch_bounds__(64) k_integrate_solo(KParams P, Work W, Cont C)
+{
+    tail_run<CE, 1>(P, W, C, C, 0, 8);
 }
 
 __global__ void k_reset_counters(unsigned long long* q, int n)
@@ -279,10 +314,15 @@ extern "C" int iat_integrate(const iat_system* sys, const iat_species* species, 
         const int64_t lim = L.max_suspended > 0 ? std::min<int64_t>(L.max_suspended, kMaxSuspended) : kMaxSuspended;
         cap = P.budget > 0 ? std::min<int64_t>(n, lim) : 0;
     }
+    // second level: trajectories still running after budget2 steps in the four-lane tail finish
+    // one per wave in k_integrate_solo
+    int budget2 = L.tail_budget > 0 ? L.tail_budget : (L.tail_budget == 0 ? (int)kDefaultTailBudget : 0);
+    const int64_t cap2 = (cap > 0 && budget2 > 0) ? std::min<int64_t>(cap, kMaxSolo) : 0;
+    if (cap2 == 0) budget2 = 0;
     // one stream-ordered block: queue counters | work buffer | continuation records
     const size_t rec = 26 * sizeof(double) + 8 * sizeof(int32_t) + sizeof(int64_t);
     const size_t work_bytes = (size_t)n * (kWorkDoubles * sizeof(double) + kWorkInts * sizeof(int32_t));
-    const size_t bytes = 256 + ((work_bytes + 255) / 256) * 256 + (size_t)cap * rec;
+    const size_t bytes = 256 + ((work_bytes + 255) / 256) * 256 + (size_t)(cap + cap2) * rec;
     void* ws = nullptr;
     if (hipMallocAsync(&ws, bytes, st) != hipSuccess) return set_error(IAT_EHIP, "hipMallocAsync of %zu bytes failed", bytes);
     unsigned long long* q = (unsigned long long*)ws;
@@ -297,8 +337,15 @@ extern "C" int iat_integrate(const iat_system* sys, const iat_species* species, 
     C.d = (double*)((char*)ws + 256 + ((work_bytes + 255) / 256) * 256);
     C.n = (int32_t*)(C.d + 26 * cap);
     C.id = (int64_t*)(C.n + 8 * cap);
+    Cont C2;
+    C2.count = q + 3;
+    C2.head = q + 4;
+    C2.cap = cap2;
+    C2.d = (double*)(C.id + cap);
+    C2.n = (int32_t*)(C2.d + 26 * cap2);
+    C2.id = (int64_t*)(C2.n + 8 * cap2);
     PhaseTimer timer(L.kernel_ms, st);
-    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, st, q, 4);
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, st, q, 5);
     timer.mark(0);
     hipLaunchKernelGGL(k_setup, dim3(nblk), dim3(256), 0, st, P, W);
     timer.mark(1);
@@ -308,6 +355,7 @@ extern "C" int iat_integrate(const iat_system* sys, const iat_species* species, 
     const void* k_plain = ce ? (const void*)k_integrate_plain<true> : (const void*)k_integrate_plain<false>;
     const void* k_pers = ce ? (const void*)k_integrate_persistent<true> : (const void*)k_integrate_persistent<false>;
     const void* k_tail = ce ? (const void*)k_integrate_tail<true> : (const void*)k_integrate_tail<false>;
+    const void* k_solo = ce ? (const void*)k_integrate_solo<true> : (const void*)k_integrate_solo<false>;
     if (L.kernel == IAT_KERNEL_PLAIN) {
         void* args[] = {&P, &W};
         launch_err = hipLaunchKernel(k_plain, dim3((unsigned)((n + L.block - 1) / L.block)), dim3(L.block), args, 0, st);
@@ -330,15 +378,26 @@ extern "C" int iat_integrate(const iat_system* sys, const iat_species* species, 
             int64_t blocks4 = (int64_t)n_cu * per_cu4;
             const int64_t need4 = (4 * cap + 255) / 256;
             if (blocks4 > need4) blocks4 = need4;
-            void* args4[] = {&P, &W, &C};
+            void* args4[] = {&P, &W, &C, &C2, &budget2};
             const hipError_t e4 = hipLaunchKernel(k_tail, dim3((unsigned)blocks4), dim3(256), args4, 0, st);
             if (launch_err == hipSuccess) launch_err = e4;
         }
+        timer.mark(3);
+        if (cap2 > 0) {
+            // one wave per block, one block per SIMD: each survivor runs without neighbours
+            const int64_t blocks1 = std::min<int64_t>((int64_t)n_cu * 4, cap2);
+            void* args1[] = {&P, &W, &C2};
+            const hipError_t e1 = hipLaunchKernel(k_solo, dim3((unsigned)blocks1), dim3(64), args1, 0, st);
+            if (launch_err == hipSuccess) launch_err = e1;
+        }
     }
-    if (L.kernel == IAT_KERNEL_PLAIN) timer.mark(2);
-    timer.mark(3);
-    hipLaunchKernelGGL(k_observe, dim3(nblk), dim3(256), 0, st, P, W);
+    if (L.kernel == IAT_KERNEL_PLAIN) {
+        timer.mark(2);
+        timer.mark(3);
+    }
     timer.mark(4);
+    hipLaunchKernelGGL(k_observe, dim3(nblk), dim3(256), 0, st, P, W);
+    timer.mark(5);
     if (hipFreeAsync(ws, st) != hipSuccess) return set_error(IAT_EHIP, "hipFreeAsync failed");
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = launch_err;

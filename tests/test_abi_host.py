@@ -32,7 +32,7 @@ def test_struct_layouts_match_header_sizes():
     assert ctypes.sizeof(_abi.System) == 8 * 21 + 8 + 8
     assert ctypes.sizeof(_abi.Gen) == 64 + 8 * 30 + 16 + 8
     assert ctypes.sizeof(_abi.Obs) == 12 * 8
-    assert ctypes.sizeof(_abi.Launch) == 32 + 8
+    assert ctypes.sizeof(_abi.Launch) == 8 * 4 + 8 * 2
 
 
 def _call(system=None, species=None, n_species=None, batch=None, obs=None, launch=None):
@@ -76,6 +76,13 @@ def test_validation_rejects_bad_arguments_without_gpu():
     la = api.launch_struct("plain", block=100)
     rc, msg = _call(launch=la, obs=_obs_dummy())
     assert rc == _abi.IAT_EINVAL and "block" in msg
+    la = api.launch_struct(tail_budget=-2)
+    rc, msg = _call(launch=la, obs=_obs_dummy())
+    assert rc == _abi.IAT_EINVAL and "tail_budget" in msg
+    la = api.launch_struct()
+    la.reserved = 1
+    rc, msg = _call(launch=la, obs=_obs_dummy())
+    assert rc == _abi.IAT_EINVAL and "reserved" in msg
     g = W.Generator(kind="sweep", species=[0, 7], E_range=(1e-12, 1e-11), q_range=(0.1, 0.2),
                     De_range=(1e-6, 1e-5))
     rc, msg = _call(batch=api.batch_struct(0, g), obs=_obs_dummy())

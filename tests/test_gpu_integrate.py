@@ -125,7 +125,10 @@ def test_plain_and_persistent_are_bitwise_identical():
         a = run(w, n=n, kernel="plain")
         for kw in (dict(block=256), dict(block=64, refill_every=4), dict(block=128, blocks_per_cu=1),
                    dict(step_budget=-1), dict(step_budget=7), dict(step_budget=500, refill_every=3),
-                   dict(step_budget=7, max_suspended=5)):          # most cannot be suspended
+                   dict(step_budget=7, max_suspended=5),            # most cannot be suspended
+                   dict(step_budget=7, tail_budget=11),             # most finish in the solo kernel
+                   dict(step_budget=5, tail_budget=3, max_suspended=40),   # solo records run out
+                   dict(step_budget=7, tail_budget=-1)):
             b = run(w, n=n, kernel="persistent", **kw)
             for k in a:
                 assert np.array_equal(a[k], b[k], equal_nan=True), (w.name, kw, k)
@@ -134,7 +137,7 @@ def test_plain_and_persistent_are_bitwise_identical():
 def test_full_size_grid_sampled_against_oracle():
     """1024x1024 grid in the benchmark's launch configuration; sampled ids checked one by one."""
     w = W.config2()
-    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    stats = api.new_stats()
     out = api.integrate_workload(w, y_final=True, stats=stats)
     torch.cuda.synchronize()
     got = PT.to_numpy(out)
@@ -148,6 +151,15 @@ def test_full_size_grid_sampled_against_oracle():
     assert np.array_equal(got["n_rhs"][ran], expect[ran])
     s = stats.cpu().numpy()
     assert s[3] == w.n and s[0] == got["n_rhs"].sum() and s[1] == got["n_accept"].sum()
+    # every attempted step is counted once, whichever of the three kernels ran it; the longest
+    # complexes of this grid outlive both budgets and finish in the solo kernel
+    assert s[5] == (got["n_accept"] + got["n_reject"]).sum()
+    # (the budgets count attempted steps; a trajectory whose exit search starts on the budget's own
+    # step is suspended with exactly that many)
+    att = got["n_accept"] + got["n_reject"]
+    assert int((att > 70000).sum()) <= s[9] <= int((att >= 70000).sum()) and s[9] > 0
+    assert int((att > 20000).sum()) <= s[7] + s[9] <= int((att >= 20000).sum())
+    assert 0 < s[8] and s[6] + s[8] < s[0]
     rng = np.random.default_rng(11)
     ids = np.sort(rng.choice(w.n, size=96, replace=False))
     P, ref = oracle_run(w, ids)
