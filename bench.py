@@ -56,6 +56,10 @@ def parse():
                     help="only time trajectory ID of the workload alone (four-lane tail and one-lane forms) "
                          "and print the per-step latency")
     ap.add_argument("--max-steps", type=int, default=0, help="accepted-step cap for --latency (0: the default)")
+    ap.add_argument("--compare-solo", type=int, default=0, metavar="ROUNDS",
+                    help="only time whole passes with the solo level (default tail budget) and without it "
+                         "(tail budget -1), alternating, ROUNDS of each: the GPU clock under a lone wave "
+                         "drifts between runs, so the two are compared pass by pass")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration) and exit")
     return ap.parse_args()
@@ -377,6 +381,30 @@ def calibrate_copy(nbytes, reps):
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "reps": reps}), flush=True)
 
 
+def compare_solo(args):
+    """Paired passes with and without the solo level (tail_budget 0 and -1), alternating which goes
+    first; prints one JSON line with every pass's phase durations and the means."""
+    import torch
+    from paper_2509_15117_amd import api
+    torch.cuda.set_device(0)
+    w = workload(args.workload)
+    out = api.alloc_obs(w.n, torch.device("cuda", 0), counters=False)
+    api.integrate_workload(w, out=out)          # warm-up
+    runs = {"solo": [], "no_solo": []}
+    for k in range(args.compare_solo):
+        order = (("no_solo", -1), ("solo", 0)) if k % 2 == 0 else (("solo", 0), ("no_solo", -1))
+        for name, tb in order:
+            ms = api.phase_ms()
+            api.integrate_workload(w, out=out, kernel_ms=ms, tail_budget=tb)
+            runs[name].append([float(x) for x in ms])
+            print(f"[bench] round {k + 1}/{args.compare_solo} {name}: {sum(ms):.0f} ms", file=sys.stderr, flush=True)
+    tot = {k: [sum(x) for x in v] for k, v in runs.items()}
+    res = {"workload": w.name, "rounds": args.compare_solo, "passes_ms": runs,
+           "mean_ms": {k: sum(v) / len(v) for k, v in tot.items()},
+           "solo_faster_in": sum(a < b for a, b in zip(tot["solo"], tot["no_solo"]))}
+    print(json.dumps(res), flush=True)
+
+
 def lone_latency(args):
     """One trajectory alone on the GPU: the critical path of a batch is its longest trajectory's step
     count times this per-step latency."""
@@ -405,6 +433,8 @@ def main():
     args = parse()
     if args.latency >= 0:
         return lone_latency(args)
+    if args.compare_solo > 0:
+        return compare_solo(args)
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy, 3)
         return
