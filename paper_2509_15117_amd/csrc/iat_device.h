@@ -926,13 +926,22 @@ __device__ __forceinline__ void traj1_advance(const KParams& P, Traj1& T)
 // with the same expressions as the one-lane form, so both give the same bits.  Every branch
 // depends on quad-uniform values only, so the four lanes of a quad stay converged.
 // ---------------------------------------------------------------------------------------
-template <int SRC>
+// Lane SRC of each quad to the whole quad: two 32-bit quad-permute moves.  ROW: the caller's quad is
+// lanes 0-3 and the only live lanes of its row of 16 (one trajectory per wave), so the row
+// broadcast of lane SRC does the same in one 64-bit move.
+template <int SRC, bool ROW = false>
 __device__ __forceinline__ double quad_bcast(double v)
 {
-    constexpr int ctrl = SRC | (SRC << 2) | (SRC << 4) | (SRC << 6);
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
+    if constexpr (ROW) {
+        const int64_t x = __builtin_bit_cast(int64_t, v);
+        const int64_t y = __builtin_amdgcn_mov_dpp(x, 0x150 + SRC, 0xF, 0xF, false);
+        return __builtin_bit_cast(double, y);
+    } else {
+        constexpr int ctrl = SRC | (SRC << 2) | (SRC << 4) | (SRC << 6);
+        const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xF, 0xF, false);
+        const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xF, 0xF, false);
+        return __hiloint2double(hi, lo);
+    }
 }
 __device__ __forceinline__ double quad_max(double v)
 {
@@ -954,6 +963,7 @@ __device__ __forceinline__ int quad_or(int v)
 // Stage cosines for the four-lane form: the values of stage_cos, with its six polynomial
 // evaluations (the phase remainder and the five stage offsets) shared out over the quad's lanes
 // in two rounds and gathered with quad moves.
+template <bool ROW = false>
 __device__ __forceinline__ StageCos stage_cos4(double tau, double phase0, double h, const Tab& T = kTab)
 {
     const int l = __lane_id() & 3;
@@ -972,13 +982,13 @@ __device__ __forceinline__ StageCos stage_cos4(double tau, double phase0, double
     small_sincos(a1, cA, sA);
     small_sincos(a2, cB, sB);
     double sb, cb;
-    phase_quadrant(k, quad_bcast<0>(cA), quad_bcast<0>(sA), sb, cb);
+    phase_quadrant(k, quad_bcast<0, ROW>(cA), quad_bcast<0, ROW>(sA), sb, cb);
     StageCos C;
-    C.c2 = cos_comb(cb, sb, quad_bcast<1>(cA), quad_bcast<1>(sA));
-    C.c3 = cos_comb(cb, sb, quad_bcast<2>(cA), quad_bcast<2>(sA));
-    C.c4 = cos_comb(cb, sb, quad_bcast<3>(cA), quad_bcast<3>(sA));
-    C.c5 = cos_comb(cb, sb, quad_bcast<0>(cB), quad_bcast<0>(sB));
-    C.c6 = cos_comb(cb, sb, quad_bcast<1>(cB), quad_bcast<1>(sB));
+    C.c2 = cos_comb(cb, sb, quad_bcast<1, ROW>(cA), quad_bcast<1, ROW>(sA));
+    C.c3 = cos_comb(cb, sb, quad_bcast<2, ROW>(cA), quad_bcast<2, ROW>(sA));
+    C.c4 = cos_comb(cb, sb, quad_bcast<3, ROW>(cA), quad_bcast<3, ROW>(sA));
+    C.c5 = cos_comb(cb, sb, quad_bcast<0, ROW>(cB), quad_bcast<0, ROW>(sB));
+    C.c6 = cos_comb(cb, sb, quad_bcast<1, ROW>(cB), quad_bcast<1, ROW>(sB));
     return C;
 }
 
@@ -990,11 +1000,12 @@ struct Traj4 {
 
 __device__ __forceinline__ int quad_axis() { return min((int)(__lane_id() & 3), 2); }
 
+template <bool ROW = false>
 __device__ __forceinline__ void accel4(const KParams& P, const Lane& L, int k, double cs, double Xa, double Xi,
                                        double& Aa, double& Ai)
 {
     const double dk = Xa - Xi;
-    const double d0 = quad_bcast<0>(dk), d1 = quad_bcast<1>(dk), d2 = quad_bcast<2>(dk);
+    const double d0 = quad_bcast<0, ROW>(dk), d1 = quad_bcast<1, ROW>(dk), d2 = quad_bcast<2, ROW>(dk);
     const double s = force_scale(L, d0, d1, d2);
     const double qc = L.qx_half * cs;
     const double kA = k == 0 ? P.kA[0] : (k == 1 ? P.kA[1] : P.kA[2]);
@@ -1034,7 +1045,7 @@ __device__ inline void traj4_start(const KParams& P, const Work& W, int64_t i, T
 
 // One attempted step of the four-lane form.  Returns the StepOutcome, or -1 when the trajectory
 // stopped before stepping (step cap, step underflow); h_used receives the step size tried.
-template <bool CE = false>
+template <bool CE = false, bool ROW = false>
 __device__ __forceinline__ int traj4_step_k(const KParams& P, const StepK& K, Traj4& T, double& h_used,
                                             const Tab& B)
 {
@@ -1046,15 +1057,15 @@ __device__ __forceinline__ int traj4_step_k(const KParams& P, const StepK& K, Tr
     const bool exiting = T.S.mode != 0;
     const int k = quad_axis();
     const double hh = h * h;
-    const StageCos C = stage_cos4(T.S.tau, T.L.phase0, h, B);
+    const StageCos C = stage_cos4<ROW>(T.S.tau, T.L.phase0, h, B);
     double F2a, F2i, F3a, F3i, F4a, F4i, F5a, F5i, F6a, F6i;
-    accel4(P, T.L, k, C.c2, stage2(T.xa, T.va, h, B), stage2(T.xi, T.vi, h, B), F2a, F2i);
-    accel4(P, T.L, k, C.c3, stage3(T.xa, T.va, h, hh, T.F1a, B), stage3(T.xi, T.vi, h, hh, T.F1i, B), F3a, F3i);
-    accel4(P, T.L, k, C.c4, stage4(T.xa, T.va, h, hh, T.F1a, F2a, B), stage4(T.xi, T.vi, h, hh, T.F1i, F2i, B), F4a,
+    accel4<ROW>(P, T.L, k, C.c2, stage2(T.xa, T.va, h, B), stage2(T.xi, T.vi, h, B), F2a, F2i);
+    accel4<ROW>(P, T.L, k, C.c3, stage3(T.xa, T.va, h, hh, T.F1a, B), stage3(T.xi, T.vi, h, hh, T.F1i, B), F3a, F3i);
+    accel4<ROW>(P, T.L, k, C.c4, stage4(T.xa, T.va, h, hh, T.F1a, F2a, B), stage4(T.xi, T.vi, h, hh, T.F1i, F2i, B), F4a,
            F4i);
-    accel4(P, T.L, k, C.c5, stage5(T.xa, T.va, h, hh, T.F1a, F2a, F3a, B),
+    accel4<ROW>(P, T.L, k, C.c5, stage5(T.xa, T.va, h, hh, T.F1a, F2a, F3a, B),
            stage5(T.xi, T.vi, h, hh, T.F1i, F2i, F3i, B), F5a, F5i);
-    accel4(P, T.L, k, C.c6, stage6(T.xa, T.va, h, hh, T.F1a, F2a, F3a, F4a, B),
+    accel4<ROW>(P, T.L, k, C.c6, stage6(T.xa, T.va, h, hh, T.F1a, F2a, F3a, F4a, B),
            stage6(T.xi, T.vi, h, hh, T.F1i, F2i, F3i, F4i, B), F6a, F6i);
     const double x5a = sol_x(T.xa, T.va, h, hh, T.F1a, F2a, F3a, F4a, F5a, B);
     const double x5i = sol_x(T.xi, T.vi, h, hh, T.F1i, F2i, F3i, F4i, F5i, B);
@@ -1063,7 +1074,7 @@ __device__ __forceinline__ int traj4_step_k(const KParams& P, const StepK& K, Tr
     double en = 0.0, F7a = 0.0, F7i = 0.0;
     bool finite = true;
     if (!exiting) {
-        accel4(P, T.L, k, C.c6, x5a, x5i, F7a, F7i);
+        accel4<ROW>(P, T.L, k, C.c6, x5a, x5i, F7a, F7i);
         const double ra = err_ratio(err_x(hh, T.F1a, F2a, F3a, F4a, F5a, F6a, B), T.xa, x5a, K.rtol, K.atol);
         const double ri = err_ratio(err_x(hh, T.F1i, F2i, F3i, F4i, F5i, F6i, B), T.xi, x5i, K.rtol, K.atol);
         const double rva = err_ratio(err_v(h, T.F1a, F3a, F4a, F5a, F6a, F7a, B), T.va, v5a, K.rtol, K.atol);
@@ -1076,16 +1087,16 @@ __device__ __forceinline__ int traj4_step_k(const KParams& P, const StepK& K, Tr
         finite = nonfin == 0;
     }
     const double dk = x5a - x5i, wk = v5a - v5i;
-    const double d0 = quad_bcast<0>(dk), d1 = quad_bcast<1>(dk), d2 = quad_bcast<2>(dk);
-    const double w0 = quad_bcast<0>(wk), w1 = quad_bcast<1>(wk), w2 = quad_bcast<2>(wk);
+    const double d0 = quad_bcast<0, ROW>(dk), d1 = quad_bcast<1, ROW>(dk), d2 = quad_bcast<2, ROW>(dk);
+    const double w0 = quad_bcast<0, ROW>(wk), w1 = quad_bcast<1, ROW>(wk), w2 = quad_bcast<2, ROW>(wk);
     const double rho_new = dot3(d0, d1, d2, d0, d1, d2);
     const double s_new = dot3(d0, d1, d2, w0, w1, w2);
     const double ww = dot3(w0, w1, w2, w0, w1, w2);
     double e_prev = 0.0, e_new = 0.0, se_new = 0.0;
     if (CE) {
-        const double p0 = quad_bcast<0>(T.xa), p1 = quad_bcast<1>(T.xa), p2 = quad_bcast<2>(T.xa);
-        const double a0 = quad_bcast<0>(x5a), a1 = quad_bcast<1>(x5a), a2 = quad_bcast<2>(x5a);
-        const double u0 = quad_bcast<0>(v5a), u1 = quad_bcast<1>(v5a), u2 = quad_bcast<2>(v5a);
+        const double p0 = quad_bcast<0, ROW>(T.xa), p1 = quad_bcast<1, ROW>(T.xa), p2 = quad_bcast<2, ROW>(T.xa);
+        const double a0 = quad_bcast<0, ROW>(x5a), a1 = quad_bcast<1, ROW>(x5a), a2 = quad_bcast<2, ROW>(x5a);
+        const double u0 = quad_bcast<0, ROW>(v5a), u1 = quad_bcast<1, ROW>(v5a), u2 = quad_bcast<2, ROW>(v5a);
         e_prev = dot3(p0, p1, p2, p0, p1, p2);
         e_new = dot3(a0, a1, a2, a0, a1, a2);
         se_new = dot3(a0, a1, a2, u0, u1, u2);
@@ -1118,11 +1129,11 @@ __device__ __forceinline__ void traj4_advance(const KParams& P, Traj4& T, const 
     double h;
     (void)traj4_step<CE>(P, T, h, B);
 }
-template <bool CE = false>
+template <bool CE = false, bool ROW = false>
 __device__ __forceinline__ void traj4_advance_k(const KParams& P, const StepK& K, Traj4& T, const Tab& B)
 {
     double h;
-    (void)traj4_step_k<CE>(P, K, T, h, B);
+    (void)traj4_step_k<CE, ROW>(P, K, T, h, B);
 }
 
 // ---------------------------------------------------------------------------------------

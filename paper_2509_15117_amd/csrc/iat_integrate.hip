@@ -201,7 +201,7 @@ __device__ __forceinline__ void tail_run(const KParams& P, const Work& W, const 
             }
         }
         if (!__any(active)) break;
-        if (active && !T.S.done) traj4_advance_k<CE>(P, K, T, B);
+        if (active && !T.S.done) traj4_advance_k<CE, QUADS == 1>(P, K, T, B);
         ++iters;
         if (active && T.S.done) {
             traj4_store(W, i, T, lane & 3);
