@@ -228,7 +228,7 @@ __device__ __forceinline__ void tail_run(const KParams& P, const Work& W, const 
                     tail_rhs += (uint64_t)(T.S.nrhs - resumed_rhs);
                 }
                 active = false;
-                need = true;
+                need = true;   // a quad that suspends is one of the wave's QUADS quads
             } else {
                 may_suspend = false;
             }
@@ -384,7 +384,8 @@ extern "C" int iat_integrate(const iat_system* sys, const iat_species* species, 
         }
         timer.mark(3);
         if (cap2 > 0) {
-            // one wave per block, one block per SIMD: each survivor runs without neighbours
+            // one wave per block and as many blocks as the chip has SIMDs, so that the survivors
+            // run without wave neighbours and, as the dispatcher spreads them, without SIMD ones
             const int64_t blocks1 = std::min<int64_t>((int64_t)n_cu * 4, cap2);
             void* args1[] = {&P, &W, &C2};
             const hipError_t e1 = hipLaunchKernel(k_solo, dim3((unsigned)blocks1), dim3(64), args1, 0, st);
