@@ -20,7 +20,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6           # MI355X dense FP64 vector peak (AMD spec)
-FLOP_PER_RHS = 161                # algorithmic FLOP per right-hand-side evaluation
+# algorithmic FLOP, counting a division, a cosine or a power as one: 38 per right-hand-side evaluation
+# and 966 per attempted Dormand-Prince step (six evaluations plus the stage sums, the error norm and
+# the step control), i.e. 161 per evaluation
+FLOP_PER_RHS = 161
 HBM_PEAK_GBS = 8000.0
 
 
@@ -71,7 +74,7 @@ def workload(name):
             "thermal": W.fig3_thermal, "fig4": W.fig4_energy, "tangent": W.config4, "adjoint": W.config4}[name]()
 
 
-# algorithmic FLOP of the differentiation (canonical count): per attempted step of the
+# algorithmic FLOP of the differentiation (same canonical count as FLOP_PER_RHS): per attempted step of the
 # primal 966; per tangent column and step 6 x 35 + 552 = 762; the adjoint per committed step recomputes
 # the step (966) and applies one transposed column (762), after a checkpointing forward pass (966).
 FLOP_PER_STEP, FLOP_PER_COLUMN_STEP = 966, 762
