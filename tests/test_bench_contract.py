@@ -42,3 +42,29 @@ def test_traffic_is_reported_only_for_the_sources_it_was_taken_on(tmp_path):
     p.write_text(json.dumps(tr))
     assert bench.traffic_bytes(str(p), wl, "k_integrate_tail") is None
     assert bench.traffic_bytes(str(tmp_path / "missing.json"), wl, "k_integrate_tail") is None
+
+
+@pytest.mark.parametrize("name", RECORDS)
+def test_roofline_names_the_dominant_kernel_of_the_three(name):
+    """The refill pipeline has three integration kernels (persistent, four-lane tail, solo); each gets its
+    own achieved FLOP rate from its own RHS count and event-timed duration, and the roofline object is
+    the longest-running one."""
+    d = json.load(open(os.path.join(ROOT, "profiles", name)))
+    ks = {k["kernel"]: k for k in d["kernels"]}
+    assert {"k_integrate_persistent", "k_integrate_tail", "k_integrate_solo"} <= set(ks)
+    for k in ks.values():
+        assert abs(k["flop_per_launch"] - bench.FLOP_PER_RHS * k["rhs_per_launch"]) <= 1e-6 * k["flop_per_launch"]
+        assert abs(k["achieved"] - k["flop_per_launch"] / (k["avg_launch_ms"] * 1e-3) / 1e12) <= 1e-9 * k["achieved"]
+    dom = max(ks.values(), key=lambda k: k["avg_launch_ms"])
+    r = d["roofline"]
+    assert r["kernel"] == dom["kernel"] and r["achieved"] == dom["achieved"] and r["traffic"] == dom["traffic"]
+
+
+def test_headline_record_carries_the_solo_phase_and_current_traffic():
+    d = json.load(open(os.path.join(ROOT, "profiles", "bench_yb_rb_grid1024.json")))
+    assert set(d["phases_ms"]) == {"setup", "main", "tail", "solo", "observe"}
+    assert 0 < d["solo_trajectories"] < d["tail_trajectories"] < d["config"]["trajectories"]
+    # the headline line was taken while the PMC counters matched its kernel sources
+    assert isinstance(d["roofline"]["traffic"], int) and d["roofline"]["traffic"] > 0
+    cp = d["critical_path"]
+    assert abs(cp["tail_ms"] - d["phases_ms"]["tail"] - d["phases_ms"]["solo"]) < 1e-6 * cp["tail_ms"]
