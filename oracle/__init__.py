@@ -89,6 +89,7 @@ def lib():
             L.orc_tangent.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]
             L.orc_fd.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp,
                                  ctypes.c_double, dp]
+            L.orc_fd_richardson.argtypes = L.orc_fd.argtypes
         _lib = L
     return _lib
 
@@ -346,4 +347,16 @@ def fd(problem, theta, phi, E, q_ratio, rel_h=1e-6):
     rc = lib().orc_fd(_ptr(p), theta, phi, E, _dptr(qr), rel_h, _dptr(d))
     if rc != 0:
         raise RuntimeError(f"orc_fd failed ({rc})")
+    return d.reshape(3, 5)
+
+
+def fd_richardson(problem, theta, phi, E, q_ratio, rel_h=2e-6):
+    """Frozen-step central differences of the observables, replayed in extended precision (long
+    double) at steps h and h/2 and Richardson-extrapolated: (4 D(h/2) - D(h)) / 3, error O(h^4)."""
+    p = np.ascontiguousarray(np.asarray(problem, dtype=PROBLEM).reshape(1))
+    qr = np.ascontiguousarray(q_ratio, dtype=np.float64)
+    d = np.zeros(15)
+    rc = lib().orc_fd_richardson(_ptr(p), theta, phi, E, _dptr(qr), rel_h, _dptr(d))
+    if rc != 0:
+        raise RuntimeError(f"orc_fd_richardson failed ({rc})")
     return d.reshape(3, 5)

@@ -117,6 +117,10 @@ int orc_tangent(const orc_problem* p, double theta, double phi, double E, const 
                 double dobs[15], double phi_out[144], double* ftle);
 int orc_fd(const orc_problem* p, double theta, double phi, double E, const double q_ratio[3],
            double rel_h, double dobs[15]);
+/* the same frozen-step central differences with the replay in extended precision (long double),
+   extrapolated from steps h and h/2 by Richardson's (4 D(h/2) - D(h)) / 3 */
+int orc_fd_richardson(const orc_problem* p, double theta, double phi, double E, const double q_ratio[3],
+                      double rel_h, double dobs[15]);
 
 #ifdef __cplusplus
 }

@@ -413,3 +413,178 @@ int orc_fd(const orc_problem* p0, double theta, double phi, double E, const doub
     free(R.h);
     return 0;
 }
+
+/* ---------------------------------------------------------------------------
+ * Frozen-step central differences in extended precision, Richardson-extrapolated.
+ *
+ * The replay of the recorded accepted steps is a smooth map of the parameters, but evaluated in
+ * FP64 it carries round-off that the collision amplifies (~1e-11 of the observables), so a central
+ * difference of step h has a round-off floor of that over h on top of its O(h^2) truncation.  The
+ * same replay in the x87 extended format (64-bit significand, ~2^11 times less round-off) lowers
+ * that floor, and Richardson's extrapolation (4 D(h/2) - D(h))/3 of the central quotients D cancels
+ * their h^2 term, leaving O(h^4).  Every operation of the replay (start state, Runge-Kutta stages,
+ * exit secant, observables) is carried out in long double here, with its own exact-ratio tableau.
+ * ------------------------------------------------------------------------- */
+typedef long double ldbl;
+
+static const ldbl LC_[7] = {0.0L, 1.0L / 5.0L, 3.0L / 10.0L, 4.0L / 5.0L, 8.0L / 9.0L, 1.0L, 1.0L};
+static const ldbl LA_[6][5] = {
+    {0, 0, 0, 0, 0},
+    {1.0L / 5.0L, 0, 0, 0, 0},
+    {3.0L / 40.0L, 9.0L / 40.0L, 0, 0, 0},
+    {44.0L / 45.0L, -56.0L / 15.0L, 32.0L / 9.0L, 0, 0},
+    {19372.0L / 6561.0L, -25360.0L / 2187.0L, 64448.0L / 6561.0L, -212.0L / 729.0L, 0},
+    {9017.0L / 3168.0L, -355.0L / 33.0L, 46732.0L / 5247.0L, 49.0L / 176.0L, -5103.0L / 18656.0L},
+};
+static const ldbl LB_[6] = {35.0L / 384.0L, 0.0L, 500.0L / 1113.0L, 125.0L / 192.0L, -2187.0L / 6784.0L,
+                            11.0L / 84.0L};
+
+typedef struct {
+    ldbl w, m_a, m_i, C4, C8;      /* C4, C8 divided by Omega^2 */
+    ldbl a[3], q[3], phase0, r0;
+} lsys;
+
+/* the system at parameters (q_x, De), everything else from the problem */
+static void make_lsys(const orc_problem* p, ldbl qx, const double q_ratio[3], ldbl De, lsys* S)
+{
+    S->w = p->omega;
+    ldbl w2 = S->w * S->w;
+    S->m_a = p->m_atom;
+    S->m_i = p->m_ion;
+    S->C4 = (ldbl)p->C4 / w2;
+    S->C8 = (ldbl)p->C4 * (ldbl)p->C4 / (4.0L * De) / w2;
+    for (int k = 0; k < 3; ++k) {
+        S->a[k] = p->a[k];
+        S->q[k] = qx * (ldbl)q_ratio[k];
+    }
+    S->phase0 = p->phase0;
+    S->r0 = p->r0;
+}
+
+static void rhs_ld(const lsys* S, ldbl tau, const ldbl* y, ldbl* dy)
+{
+    ldbl d[3] = {y[0] - y[3], y[1] - y[4], y[2] - y[5]};
+    ldbl r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    ldbl r4 = r2 * r2, r6 = r4 * r2, r10 = r6 * r4;
+    ldbl s = 8.0L * S->C8 / r10 - 4.0L * S->C4 / r6;
+    ldbl cs = cosl(tau + S->phase0);
+    for (int k = 0; k < 3; ++k) {
+        ldbl F = s * d[k];
+        ldbl kappa = (S->a[k] + 2.0L * S->q[k] * cs) / 4.0L;
+        dy[k] = y[6 + k];
+        dy[3 + k] = y[9 + k];
+        dy[6 + k] = F / S->m_a;
+        dy[9 + k] = -F / S->m_i - kappa * y[3 + k];
+    }
+}
+
+static void rk5_ld(const lsys* S, ldbl tau, const ldbl* y, ldbl h, ldbl* out)
+{
+    ldbl k[6][NY], yt[NY];
+    rhs_ld(S, tau, y, k[0]);
+    for (int s = 1; s < 6; ++s) {
+        for (int i = 0; i < NY; ++i) {
+            ldbl acc = 0.0L;
+            for (int j = 0; j < s; ++j) acc += LA_[s][j] * k[j][i];
+            yt[i] = y[i] + h * acc;
+        }
+        rhs_ld(S, tau + LC_[s] * h, yt, k[s]);
+    }
+    for (int i = 0; i < NY; ++i) {
+        ldbl acc = 0.0L;
+        for (int j = 0; j < 6; ++j) acc += LB_[j] * k[j][i];
+        out[i] = y[i] + h * acc;
+    }
+}
+
+static ldbl sep_ld(const ldbl* y)
+{
+    ldbl d0 = y[0] - y[3], d1 = y[1] - y[4], d2 = y[2] - y[5];
+    return sqrtl(d0 * d0 + d1 * d1 + d2 * d2);
+}
+
+/* observables (angle, q_transfer, dE_ion) of the frozen-step replay at parameters v */
+static void replay_obs_ld(const orc_problem* p, const record* R, const double q_ratio[3], const ldbl v[5],
+                          ldbl out[3])
+{
+    lsys S;
+    make_lsys(p, v[3], q_ratio, v[4], &S);
+    ldbl n[3] = {sinl(v[0]) * cosl(v[1]), sinl(v[0]) * sinl(v[1]), cosl(v[0])};
+    ldbl v0 = sqrtl(2.0L * v[2] / S.m_a);     /* a.u. */
+    ldbl y[NY], yn[NY], vi[3];
+    for (int k = 0; k < 3; ++k) {
+        y[k] = S.r0 * n[k];
+        y[3 + k] = 0.0L;
+        vi[k] = -v0 * n[k];
+        y[6 + k] = vi[k] / S.w;
+        y[9 + k] = 0.0L;
+    }
+    ldbl tau = 0.0L;
+    int64_t whole = R->exited ? R->n - 1 : R->n;
+    for (int64_t s = 0; s < whole; ++s) {
+        rk5_ld(&S, tau, y, R->h[s], yn);
+        memcpy(y, yn, sizeof(y));
+        tau = (s == whole - 1 && (R->res.status & ORC_TMAX)) ? (ldbl)p->t_max * S.w : tau + R->h[s];
+    }
+    if (R->exited) {
+        ldbl hf = R->h_exit_full, yt[NY];
+        rk5_ld(&S, tau, y, hf, yn);
+        ldbl x0 = 0.0L, g0 = sep_ld(y) - S.r0, x1 = hf, g1 = sep_ld(yn) - S.r0;
+        for (int it = 0; it < 4; ++it) {
+            ldbl x2 = (g1 != g0) ? x1 - g1 * (x1 - x0) / (g1 - g0) : x1;
+            if (x2 < 0.0L) x2 = 0.0L;
+            if (x2 > hf) x2 = hf;
+            rk5_ld(&S, tau, y, x2, yt);
+            ldbl g2 = sep_ld(yt) - S.r0;
+            x0 = x1;
+            g0 = g1;
+            x1 = x2;
+            g1 = g2;
+        }
+        memcpy(y, yt, sizeof(y));
+        tau += x1;
+    }
+    ldbl vf[3] = {y[6] * S.w, y[7] * S.w, y[8] * S.w};
+    ldbl cx = vi[1] * vf[2] - vi[2] * vf[1], cy = vi[2] * vf[0] - vi[0] * vf[2], cz = vi[0] * vf[1] - vi[1] * vf[0];
+    out[0] = atan2l(sqrtl(cx * cx + cy * cy + cz * cz), vi[0] * vf[0] + vi[1] * vf[1] + vi[2] * vf[2]);
+    ldbl d0 = vf[0] - vi[0], d1 = vf[1] - vi[1], d2 = vf[2] - vi[2];
+    out[1] = S.m_a * sqrtl(d0 * d0 + d1 * d1 + d2 * d2);
+    ldbl cs = cosl(tau + S.phase0), e = 0.0L;
+    for (int k = 0; k < 3; ++k) {
+        ldbl u = y[9 + k] * S.w;
+        e += 0.5L * S.m_i * u * u + (S.a[k] + 2.0L * S.q[k] * cs) * S.m_i * S.w * S.w * y[3 + k] * y[3 + k] / 8.0L;
+    }
+    out[2] = e;                      /* E_ion(0) = 0 for the head-on start */
+}
+
+int orc_fd_richardson(const orc_problem* p0, double theta, double phi, double E, const double q_ratio[3],
+                      double rel_h, double dobs[15])
+{
+    if (p0->exit_centre) return -2;   /* head-on problems only */
+    orc_problem p = *p0;
+    double y0[12], dth[12], dph[12], dEy[12];
+    headon_internal(&p, theta, phi, E, y0, dth, dph, dEy);
+    for (int k = 0; k < 12; ++k) p.y0[k] = k < 6 ? y0[k] : y0[k] * p.omega;
+    record R;
+    if (primal_record(&p, &R) != 0) return -1;
+    double qx = p.q[0] / (q_ratio[0] != 0.0 ? q_ratio[0] : 1.0);
+    ldbl base[5] = {theta, phi, E, qx, p.De};
+    double ref[5] = {1.0, 1.0, fabs(E), fmax(fabs(qx), 0.1), fabs(p.De)};
+    for (int pi = 0; pi < 5; ++pi) {
+        ldbl h = (ldbl)rel_h * (ldbl)fmax(fabs((double)base[pi]), ref[pi]);
+        ldbl D[2][3];
+        for (int lev = 0; lev < 2; ++lev) {
+            ldbl hl = lev == 0 ? h : h / 2.0L, o[2][3];
+            for (int sgn = 0; sgn < 2; ++sgn) {
+                ldbl v[5];
+                for (int j = 0; j < 5; ++j) v[j] = base[j];
+                v[pi] += sgn == 0 ? hl : -hl;
+                replay_obs_ld(&p, &R, q_ratio, v, o[sgn]);
+            }
+            for (int k = 0; k < 3; ++k) D[lev][k] = (o[0][k] - o[1][k]) / (2.0L * hl);
+        }
+        for (int k = 0; k < 3; ++k) dobs[k * 5 + pi] = (double)((4.0L * D[1][k] - D[0][k]) / 3.0L);
+    }
+    free(R.h);
+    return 0;
+}
