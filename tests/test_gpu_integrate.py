@@ -32,23 +32,7 @@ def oracle_run(w, ids):
 
 
 def assert_parity(P, ref, got, name, min_direct=1):
-    rates = []
-    direct, spread, rest = PT.classify(P, ref, got, step_rates=rates)
-    n_strict = int(np.sum(spread <= 0.1 * PT.REL))
-    print(f"{name}: {len(direct)} direct ({n_strict} with round-off spread <= 1e-9, bar 1e-8), "
-          f"{len(rest)} in ensemble", flush=True)
-    assert len(direct) >= min_direct, f"{name}: only {len(direct)} direct trajectories"
-    bad = PT.per_trajectory_mismatches(P, ref, got, direct, check_counts=False, spread=spread)
-    assert not bad, f"{name}: per-trajectory mismatches {bad[:10]} (of {len(direct)})"
-    same = np.mean([got["n_accept"][i] == ref["n_accept"][i] and got["n_reject"][i] == ref["n_reject"][i]
-                    for i in direct]) if len(direct) else 1.0
-    # step counts: identical on >= 99 %, or, where round-off alone changes the oracle's own step
-    # sequence more often (its five probes), on all but twice the probes' worst rate
-    allowed = max(0.01, 2.0 * max(rates, default=0.0))
-    assert 1 - same <= allowed, (f"{name}: step counts differ on {1 - same:.1%} of direct trajectories "
-                                 f"(the oracle's round-off probes: {[f'{r:.1%}' for r in rates]})")
-    badE = PT.ensemble_mismatches(ref, got, rest)
-    assert not badE, f"{name}: ensemble mismatches {badE}"
+    direct, rest, _ = PT.check_parity(P, ref, got, name, min_direct=min_direct)
     return direct, rest
 
 
@@ -296,3 +280,17 @@ def test_trap_off_two_body_invariants_on_the_gpu():
         print(f"b = {bs[j]:6.0f} a0: bounces {got['n_bounce'][j]}, energy drift {dE:.1e} De, "
               f"angular momentum {dL:.1e}, centre of mass {np.abs(R).max() / r0:.1e} r0", flush=True)
         assert dE < 1e-10 and dL < 1e-10 and np.abs(R).max() < 1e-9 * r0
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_linear_trap_parity(kernel):
+    """The linear trap of the Fig. 1 discussion (q_y = -q_x, no RF along z): the whole 8x8 grid and a
+    ragged slice of the 64x64 grid, direct trajectories one by one, the rest in ensemble."""
+    for side, id0, n, min_direct in ((8, 0, 64, 8), (64, 1000, 777, 100)):
+        w = W.headon_grid(side, f"yb_rb_headon_grid_{side}x{side}_linear")
+        w.system.a_ratio, w.system.q_ratio = W.LINEAR
+        w.system.max_steps = 2_000_000
+        got = run(w, n=n, id0=id0, kernel=kernel)
+        P, ref = oracle_run(w, np.arange(id0, id0 + n))
+        assert np.all(P["q"][:, 1] == -P["q"][:, 0]) and np.all(P["q"][:, 2] == 0.0)
+        assert_parity(P, ref, got, f"linear{side}/{kernel}", min_direct=min_direct)

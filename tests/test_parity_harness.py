@@ -1,0 +1,46 @@
+"""CPU checks of the parity harness itself (tests/_parity.py), with the oracle's FMA twin standing in
+for the library: the twin is a legitimate arithmetic variant, so the harness must accept it; a planted
+error in one field (on a copy of the twin's outputs, on the CPU) must be caught."""
+import numpy as np
+
+import oracle
+import workloads as W
+from tests import _parity as PT
+
+oracle.build()
+
+
+def _twin_outputs(P):
+    g = PT.as_outputs(oracle.integrate(P, twin=True))
+    return {k: np.array(v) for k, v in g.items()}
+
+
+def test_harness_accepts_the_twin_on_the_grid_and_a_sweep_slice():
+    for w, ids, min_direct in ((W.config1(), np.arange(64), 16),
+                               (W.config3(), np.arange(1_234_567, 1_234_567 + 300), 100)):
+        P = oracle.problems_for(w, ids)
+        ref = oracle.integrate(P)
+        got = _twin_outputs(P)
+        direct, rest, rep = PT.check_parity(P, ref, got, w.name, min_direct=min_direct)
+        assert rep["max_bar"] <= PT.MAX_BAR and len(direct) + len(rest) == len(ids)
+
+
+def test_harness_catches_a_shifted_bounce_time_and_a_wrong_lifetime_distribution():
+    w = W.config1()
+    P = oracle.problems_for(w, np.arange(64))
+    ref = oracle.integrate(P)
+    got = _twin_outputs(P)
+    direct, spread, rest = PT.classify(P, ref, got)
+    i = int(direct[np.argmax(ref["n_bounce"][direct])])
+    assert ref["n_bounce"][i] == 1
+    bad = dict(got)
+    bad["t_bounce_first"] = got["t_bounce_first"].copy()
+    bad["t_bounce_first"][i] *= 1.0 + 1e-6
+    hits = PT.bounce_time_mismatches(P, ref, bad, direct, spread)
+    assert [h[:2] for h in hits] == [(i, "t_bounce_first")]
+    # complexes whose lifetimes all collapse to zero: the survival check fails
+    flat = dict(got)
+    flat["t_bounce_last"] = got["t_bounce_first"].copy()
+    flat["status"] = got["status"].copy()
+    assert PT.survival_mismatches(ref, flat, rest)
+    assert not PT.survival_mismatches(ref, got, rest)
