@@ -63,7 +63,7 @@ extern "C" {
                                           checkpoints did not fit the workspace): NaN       */
 
 #define IAT_MAX_SPECIES 8
-#define IAT_DEFAULT_MAX_STEPS 20000000LL  /* used when iat_system.max_steps == 0 */
+#define IAT_MAX_STEPS_LIMIT (1LL << 28)   /* largest accepted-step cap (range of the step counters) */
 
 /* One atomic species: mass (m_e) and C4 = alpha/2 (a.u.). */
 typedef struct {
@@ -88,7 +88,8 @@ typedef struct {
     double rtol, atol;        /* error tolerances on the internal state                 */
     double h0, hmax, hmin;    /* tau units; 0 -> 2pi*1e-3, 2pi/8, 1e-6*h0               */
     double r_bounce_over_rm;  /* bounce = periapsis inside this many r_m; 0 -> 1        */
-    int64_t max_steps;        /* accepted-step cap; 0 -> IAT_DEFAULT_MAX_STEPS          */
+    int64_t max_steps;        /* accepted-step cap (status MAX_STEPS); 0 = no cap short of
+                                 IAT_MAX_STEPS_LIMIT; above the limit: IAT_EINVAL         */
 } iat_system;
 
 enum { IAT_GEN_ARRAYS = 0, IAT_GEN_GRID = 1, IAT_GEN_SWEEP = 2, IAT_GEN_THERMAL = 3 };

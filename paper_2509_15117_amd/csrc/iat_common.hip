@@ -80,6 +80,9 @@ int validate_common(const iat_system* sys, const iat_species* species, int n_spe
     if (!finite_pos(sys->rtol) || !finite_pos(sys->atol)) return set_error(IAT_EINVAL, "rtol and atol must be > 0");
     if (sys->h0 < 0 || sys->hmax < 0 || sys->hmin < 0 || sys->r_bounce_over_rm < 0 || sys->max_steps < 0)
         return set_error(IAT_EINVAL, "h0, hmax, hmin, r_bounce_over_rm and max_steps must be >= 0");
+    if (sys->max_steps > IAT_MAX_STEPS_LIMIT)
+        return set_error(IAT_EINVAL, "max_steps %lld is above the limit of the step counters (%lld)",
+                         (long long)sys->max_steps, (long long)IAT_MAX_STEPS_LIMIT);
     if (sys->t_max * sys->omega_rf + std::fabs(sys->phase0) > 1.5e6)
         return set_error(IAT_EINVAL, "Omega t_max must stay below 1.5e6 RF radians (phase reduction range)");
     if (sys->hmax > kTwoPi / 8.0)
@@ -167,7 +170,7 @@ void fill_params(KParams& P, const iat_system* sys, const iat_species* species, 
     P.rb_ratio2 = P.r_bounce_over_rm * P.r_bounce_over_rm;
     P.inv_mi = 1.0 / sys->m_ion;
     for (int k = 0; k < 3; ++k) P.kA[k] = 0.25 * (sys->a_x * sys->a_ratio[k]);
-    P.max_steps = sys->max_steps > 0 ? sys->max_steps : IAT_DEFAULT_MAX_STEPS;
+    P.max_steps = sys->max_steps > 0 ? sys->max_steps : IAT_MAX_STEPS_LIMIT;
     for (int s = 0; s < n_species; ++s) {
         P.sp_m[s] = species[s].m_atom;
         P.sp_C4[s] = species[s].C4;

@@ -105,6 +105,15 @@ def test_validation_rejects_bad_arguments_without_gpu():
     s.hmax = 1.0                                     # > pi/4: beyond an eighth of the RF period
     rc, msg = _call(system=s, obs=_obs_dummy())
     assert rc == _abi.IAT_EINVAL and "hmax" in msg
+    # the accepted-step cap must fit the device's step counters
+    limit = 1 << 28
+    txt = open(os.path.join(ROOT, "include", "iat.h")).read()
+    assert "#define IAT_MAX_STEPS_LIMIT (1LL << 28)" in txt
+    for cap, want in ((limit, 0), (limit + 1, _abi.IAT_EINVAL), (1 << 40, _abi.IAT_EINVAL), (0, 0)):
+        s = api.system_struct(w.system)
+        s.max_steps = cap
+        rc, msg = _call(system=s, obs=_obs_dummy())
+        assert rc == want and (want == 0 or "max_steps" in msg), (cap, rc, msg)
 
 
 def test_derivatives_reject_thermal_and_explicit_starts_without_gpu():

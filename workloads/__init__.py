@@ -84,7 +84,9 @@ class System:
     hmax: float = 0.0
     hmin: float = 0.0
     r_bounce_over_rm: float = 1.0
-    max_steps: int = 0
+    # accepted-step cap (a numerical safety stop, status MAX_STEPS), given to the oracle and the
+    # library alike: complexes in the deepest wells can take ~1e8 steps to reach t_max
+    max_steps: int = 20_000_000
 
 
 @dataclass
