@@ -12,7 +12,11 @@
 //   3. seed      : one lane per trajectory: dJ/dy_f and dJ/dtau_f from the observable formulas,
 //                  projected on the exit event; the explicit dependence of J on the start velocity
 //                  and on q_x is kept aside.
-//   4. reverse   : four lanes per trajectory.  The final step, then each segment from the last:
+//   4. order     : the differentiable trajectories sorted into descending buckets of log2 of their
+//                  committed steps; the reverse kernel's quads take them from this queue in order,
+//                  longest first, so the longest reverse sweeps start at once and the short ones fill
+//                  in around them (no static striding of trajectories over quads).
+//   5. reverse   : four lanes per trajectory.  The final step, then each segment from the last:
 //                  recompute the segment from its checkpoint (states kept in per-quad scratch), and
 //                  apply the step adjoints backwards.  For one step of the Nystrom form
 //                    X_s = x + c_s h v + h^2 sum_j P_sj F_j,  F_s = a(tau + c_s h, X_s),
@@ -21,7 +25,7 @@
 //                  Xbar_s = J_s^T Fbar_s (s = 6..1), then lx += sum_s Xbar_s and
 //                  lv += h lx + h sum_s c_s Xbar_s; q_x and De collect (da/dp)^T Fbar_s.
 //                  Adjoints that pass 2^400 are rescaled (exponent tracked per trajectory).
-//   5. post      : chain rule through the head-on start (theta, phi, E) and the explicit terms.
+//   6. post      : chain rule through the head-on start (theta, phi, E) and the explicit terms.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,6 +41,10 @@ constexpr int kRec = 24;           // doubles per record: lanes 0..2 hold 6 valu
 constexpr int kScr = 8;            // doubles per lane per recomputed step: x_a, x_i, v_a, v_i, F1_a, F1_i, tau, h
 constexpr int kSkip = -1;
 constexpr int kReplayFailed = -1;  // exponent value that marks a failed recomputation
+constexpr int kBuckets = 64;       // queue buckets: floor(log2(committed steps + 1))
+// control words of the reverse kernel's queue: [0] next queue position, [1] queue length,
+// [2, 2 + kBuckets) bucket sizes, [2 + kBuckets, 2 + 2 kBuckets) bucket fill cursors
+constexpr int kCtlWords = 2 + 2 * kBuckets;
 
 struct AdjBuf {
     int64_t* off;        // [n + 1] first record of each trajectory (exclusive scan of the counts)
@@ -48,19 +56,25 @@ struct AdjBuf {
     int32_t* info;       // [2][n] committed steps, state (1 = ok, kSkip = skipped)
     double* scr;         // per-quad scratch [kSeg][kScr][lanes]
     int64_t lanes;       // 4 x resident quads of the reverse kernel
+    int64_t* order;      // [n] queue of the reverse kernel: trajectory indices, longest bucket first
+    unsigned long long* ctl;   // [kCtlWords] queue control words (zeroed by the scan kernel)
 };
 
 // ---------------------------------------------------------------------------------------
 // 1. offsets: records = accepted/256 + 2 (checkpoints 0..J and the final step) for trajectories
-// that exited or reached t_max; 0 otherwise.  One block, contiguous chunks per thread.
+// that exited or reached t_max; 0 otherwise.  Exact exclusive scan over every trajectory (one block,
+// contiguous chunks per thread), off[n] = the total.  Trajectory i owns records [off[i], off[i+1]);
+// the forward pass skips every trajectory whose range ends beyond cap, so no record is ever written
+// at or past cap.  ctl, if not NULL, receives the zeroed queue control words.
 // ---------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(1024) k_adj_scan(const int64_t* n_accept, const uint32_t* status, int64_t n,
-                                                   int64_t cap, int64_t* off)
+                                                   int64_t* off, unsigned long long* ctl)
 {
     __shared__ int64_t part[1024];
     const int t = threadIdx.x;
+    if (ctl && t < kCtlWords) ctl[t] = 0ull;
     const int64_t per = (n + 1023) / 1024;
-    const int64_t lo = t * per, hi = min(n, lo + per);
+    const int64_t lo = min(n, t * per), hi = min(n, lo + per);
     int64_t s = 0;
     for (int64_t i = lo; i < hi; ++i) {
         const bool ok = (status[i] & (IAT_ST_EXITED | IAT_ST_TMAX)) != 0 && n_accept[i] >= 0;
@@ -75,19 +89,15 @@ __global__ void __launch_bounds__(1024) k_adj_scan(const int64_t* n_accept, cons
             part[j] = run;
             run += v;
         }
+        off[n] = run;
     }
     __syncthreads();
     int64_t run = part[t];
     for (int64_t i = lo; i < hi; ++i) {
         const bool ok = (status[i] & (IAT_ST_EXITED | IAT_ST_TMAX)) != 0 && n_accept[i] >= 0;
-        const int64_t m = ok ? n_accept[i] / kSeg + 2 : 0;
-        // trajectories whose records do not fit the workspace get none (skipped)
-        const bool fits = run + m <= cap;
         off[i] = run;
-        run += fits ? m : 0;
+        run += ok ? n_accept[i] / kSeg + 2 : 0;
     }
-    if (hi == n && lo < hi) off[n] = run;
-    if (n == 0 && t == 0) off[0] = 0;
 }
 
 __device__ __forceinline__ void rec_store(double* r, int lane4, double xa, double xi, double va, double vi, double fa,
@@ -115,7 +125,7 @@ __global__ void __launch_bounds__(256) k_adj_forward(KParams P, Work W, AdjBuf B
     const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 2;
     if (i >= P.n) return;
     const int64_t m = B.off[i + 1] - B.off[i];
-    if (m < 2) {       // no records (did not exit normally, or did not fit the workspace)
+    if (m < 2 || B.off[i + 1] > B.cap) {     // no records, or they do not fit the workspace
         if (lane4 == 0) {
             B.info[i] = 0;
             B.info[P.n + i] = kSkip;
@@ -282,7 +292,41 @@ __global__ void __launch_bounds__(128) k_adj_seed(KParams P, Work W, AdjBuf B, c
 }
 
 // ---------------------------------------------------------------------------------------
-// 4. reverse sweep
+// 4. queue of the reverse sweep: differentiable trajectories by descending bucket of
+// floor(log2(committed steps + 1)); within a bucket in arrival order (the order only decides which
+// quad runs a trajectory, never its bits: each quad recomputes from the records alone)
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ int step_bucket(int32_t ncom)
+{
+    return 63 - __clzll((unsigned long long)ncom + 1ull);
+}
+
+__global__ void __launch_bounds__(256) k_adj_order_count(int64_t n, AdjBuf B)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || B.info[n + i] != 1) return;
+    atomicAdd(&B.ctl[2 + step_bucket(B.info[i])], 1ull);
+}
+
+__global__ void __launch_bounds__(256) k_adj_order_fill(int64_t n, AdjBuf B)
+{
+    __shared__ unsigned long long start[kBuckets];
+    const int t = threadIdx.x;
+    if (t < kBuckets) {
+        unsigned long long s = 0;
+        for (int b = t + 1; b < kBuckets; ++b) s += B.ctl[2 + b];
+        start[t] = s;
+        if (blockIdx.x == 0 && t == 0) B.ctl[1] = s + B.ctl[2];
+    }
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + t;
+    if (i >= n || B.info[n + i] != 1) return;
+    const int b = step_bucket(B.info[i]);
+    B.order[start[b] + atomicAdd(&B.ctl[2 + kBuckets + b], 1ull)] = i;
+}
+
+// ---------------------------------------------------------------------------------------
+// 5. reverse sweep
 // ---------------------------------------------------------------------------------------
 // Xbar = J^T Fbar at one stage for this lane's axis:  with u = Fbar_a/m_a - Fbar_i/m_i,
 // Xbar_a = G u, Xbar_i = -G u - kappa Fbar_i, G = s I + 2 s'(rho) d d^T; q_x and De pick up
@@ -379,11 +423,17 @@ __global__ void __launch_bounds__(256) k_adj_reverse(KParams P, Work W, AdjBuf B
     const int lane4 = __lane_id() & 3;
     const int k = quad_axis();
     const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 2;     // resident quad
-    const int64_t nq = ((int64_t)gridDim.x * blockDim.x) >> 2;
     const int64_t gl = q * 4 + lane4;
+    if (gl >= B.lanes) return;                  // lanes beyond the scratch (quad-uniform)
     const StepK K = step_k_in_registers(P);     // latency-bound: launch constants held in registers
-    for (int64_t i = q; i < P.n; i += nq) {
-        if (B.info[P.n + i] != 1) continue;     // quad-uniform
+    const unsigned long long queued = B.ctl[1];
+    for (;;) {
+        // the quad's first lane takes the next queue position and hands it to the other three
+        unsigned long long pos = 0ull;
+        if (lane4 == 0) pos = atomicAdd(&B.ctl[0], 1ull);
+        pos = __shfl(pos, __lane_id() & ~3);
+        if (pos >= queued) break;
+        const int64_t i = B.order[pos];
         Lane L;
         work_lane(W, i, L);
         TrajParams tp;
@@ -522,7 +572,7 @@ int64_t reverse_quads(int64_t n)
 }
 
 struct AdjLayout {
-    size_t off, work, lam, acc, expl, info, scr, rec, total_fixed;
+    size_t off, work, lam, acc, expl, info, order, ctl, scr, rec, total_fixed;
     int64_t lanes;
 };
 
@@ -544,6 +594,10 @@ AdjLayout adj_layout(int64_t n)
     o += up((size_t)n * 8 * sizeof(double));
     L.info = o;
     o += up((size_t)n * 2 * sizeof(int32_t));
+    L.order = o;
+    o += up((size_t)n * sizeof(int64_t));
+    L.ctl = o;
+    o += up((size_t)kCtlWords * sizeof(unsigned long long));
     L.scr = o;
     o += up((size_t)L.lanes * kSeg * kScr * sizeof(double));
     L.rec = o;
@@ -586,7 +640,7 @@ extern "C" int iat_adjoint_workspace_bytes(const iat_system* sys, const iat_spec
     if (hipMallocAsync((void**)&off, (size_t)(n + 1) * sizeof(int64_t), st) != hipSuccess)
         return set_error(IAT_EHIP, "hipMallocAsync failed");
     hipLaunchKernelGGL(k_adj_scan, dim3(1), dim3(1024), 0, st, (const int64_t*)obs->n_accept,
-                       (const uint32_t*)obs->status, n, (int64_t)INT64_MAX / 2, off);
+                       (const uint32_t*)obs->status, n, off, (unsigned long long*)nullptr);
     int64_t total = 0;
     hipError_t e = hipMemcpyAsync(&total, off + n, sizeof(int64_t), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -632,6 +686,8 @@ extern "C" int iat_adjoint(const iat_system* sys, const iat_species* species, in
     B.expl = (double*)(base + Lo.expl);
     B.info = (int32_t*)(base + Lo.info);
     B.scr = (double*)(base + Lo.scr);
+    B.order = (int64_t*)(base + Lo.order);
+    B.ctl = (unsigned long long*)(base + Lo.ctl);
     B.rec = (double*)(base + Lo.rec);
     B.cap = (int64_t)((bytes - Lo.total_fixed) / (kRec * sizeof(double)));
     B.lanes = Lo.lanes;
@@ -640,10 +696,12 @@ extern "C" int iat_adjoint(const iat_system* sys, const iat_species* species, in
     W.D = (double*)(base + Lo.work);
     W.I = (int32_t*)(W.D + (size_t)kWorkDoubles * n);
     hipLaunchKernelGGL(k_adj_scan, dim3(1), dim3(1024), 0, st, (const int64_t*)obs->n_accept,
-                       (const uint32_t*)obs->status, n, B.cap, B.off);
+                       (const uint32_t*)obs->status, n, B.off, B.ctl);
     launch_setup(P, W, st);
     hipLaunchKernelGGL(k_adj_forward, dim3((unsigned)((4 * n + 255) / 256)), dim3(256), 0, st, P, W, B);
     hipLaunchKernelGGL(k_adj_seed, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, P, W, B, obs_bar);
+    hipLaunchKernelGGL(k_adj_order_count, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, B);
+    hipLaunchKernelGGL(k_adj_order_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, B);
     hipLaunchKernelGGL(k_adj_reverse, dim3((unsigned)(Lo.lanes / 256 + (Lo.lanes % 256 ? 1 : 0))), dim3(256), 0, st,
                        P, W, B);
     hipLaunchKernelGGL(k_adj_post, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, P, B, p_bar, y0_bar);
