@@ -344,9 +344,36 @@ def cpu_baseline(w, target_s):
     t = time.perf_counter()
     R = oracle.integrate(P, threads)
     el = time.perf_counter() - t
+    # one thread on the first ids of the same sample, about a quarter of the all-thread time; the
+    # heavy-tailed costs make RK stages/s the comparable figure between the two
+    m = max(1, min(n, int(n * 0.25 / max(threads, 1))))
+    t = time.perf_counter()
+    R1 = oracle.integrate(P[:m], 1)
+    el1 = time.perf_counter() - t
     return dict(value=n / el, unit="trajectories/s", cores=threads, kind="oracle",
                 sample=f"{n} evenly strided ids of the {w.n}-trajectory workload, {el:.1f} s",
-                rk_stages_per_s=float(R["n_rhs"].sum()) / el)
+                rk_stages_per_s=float(R["n_rhs"].sum()) / el,
+                single_core={"trajectories_per_s": m / el1, "rk_stages_per_s": float(R1["n_rhs"].sum()) / el1,
+                             "sample": f"the first {m} ids of that sample, one thread, {el1:.1f} s"},
+                host=host_description(), build="gcc -O3 -fno-fast-math -ffp-contract=off -fopenmp")
+
+
+def host_description():
+    """CPU model, logical CPUs and the CPUs this process may run on (lscpu when present)."""
+    import shutil
+    import subprocess
+    d = {"logical_cpus": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0))}
+    if shutil.which("lscpu"):
+        try:
+            txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+            for line in txt.splitlines():
+                k, _, v = line.partition(":")
+                if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core",
+                                 "CPU max MHz", "Hypervisor vendor"):
+                    d[k.strip()] = v.strip()
+        except (OSError, subprocess.SubprocessError):
+            pass
+    return d
 
 
 def sources_digest():

@@ -51,7 +51,7 @@ def build(force: bool = False) -> str:
     srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
     if not force and os.path.exists(LIB_PATH) and os.path.exists(TWIN_PATH):
         return LIB_PATH
-    base = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-fno-fast-math"]
+    base = ["gcc", "-O3", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-fno-fast-math"]
     for path, extra in ((LIB_PATH, ["-ffp-contract=off"]), (TWIN_PATH, ["-mfma", "-ffp-contract=fast"])):
         subprocess.check_call(base + extra + ["-o", path + ".tmp", *srcs, "-lm"])
         os.replace(path + ".tmp", path)
