@@ -418,106 +418,136 @@ __device__ __forceinline__ double quad_sum3(double v)
     return (a + b) + c;
 }
 
+// Reverse sweep of trajectory i by one quad: the final step, then each segment from the last, recomputed
+// from its checkpoint into the quad's scratch (lanes gl of B.scr) and swept backwards.
+__device__ inline void reverse_trajectory(const KParams& P, const Work& W, const AdjBuf& B, const StepK& K, int64_t i,
+                                          int k, int lane4, int64_t gl)
+{
+    Lane L;
+    work_lane(W, i, L);
+    TrajParams tp;
+    traj_params(P, i, tp);
+    const double inv_De = 1.0 / tp.De;
+    const int64_t m = B.off[i + 1] - B.off[i];
+    const double* R = B.rec + B.off[i] * kRec;
+    const int32_t ncom = B.info[i];
+    Adj4 A;
+    A.xa = B.lam[(int64_t)k * P.n + i];
+    A.xi = B.lam[(int64_t)(3 + k) * P.n + i];
+    A.va = B.lam[(int64_t)(6 + k) * P.n + i];
+    A.vi = B.lam[(int64_t)(9 + k) * P.n + i];
+    A.pq = A.pD = 0.0;
+    A.e2 = 0;
+    {   // the final step
+        const double* r = R + (m - 1) * kRec;
+        step_adjoint(P, L, k, inv_De, r[k * 6 + 0], r[k * 6 + 1], r[k * 6 + 2], r[k * 6 + 3], r[k * 6 + 4],
+                     r[k * 6 + 5], r[18], r[19], A);
+    }
+    for (int32_t j = ncom / kSeg; j >= 0; --j) {
+        const int32_t cnt = min(kSeg, ncom - j * kSeg);
+        if (cnt <= 0) continue;
+        // recompute the segment from its checkpoint, keeping each committed step's start
+        const double* r = R + (int64_t)j * kRec;
+        Traj4 T;
+        T.L = L;
+        scal_init(P, T.S);
+        T.xa = r[k * 6 + 0];
+        T.xi = r[k * 6 + 1];
+        T.va = r[k * 6 + 2];
+        T.vi = r[k * 6 + 3];
+        T.F1a = r[k * 6 + 4];
+        T.F1i = r[k * 6 + 5];
+        T.S.tau = r[18];
+        T.S.h = r[19];
+        T.S.nacc = 0;
+        {
+            const double dk = T.xa - T.xi, wk = T.va - T.vi;
+            const double d0 = quad_bcast<0>(dk), d1 = quad_bcast<1>(dk), d2 = quad_bcast<2>(dk);
+            const double w0 = quad_bcast<0>(wk), w1 = quad_bcast<1>(wk), w2 = quad_bcast<2>(wk);
+            T.S.rho_prev = dot3(d0, d1, d2, d0, d1, d2);
+            T.S.s_prev = dot3(d0, d1, d2, w0, w1, w2);
+        }
+        int32_t c = 0;
+        int guard = 0;
+        while (c < cnt && !T.S.done && guard < 64 * kSeg) {
+            double* sl = B.scr + (int64_t)c * kScr * B.lanes + gl;
+            sl[0 * B.lanes] = T.xa;
+            sl[1 * B.lanes] = T.xi;
+            sl[2 * B.lanes] = T.va;
+            sl[3 * B.lanes] = T.vi;
+            sl[4 * B.lanes] = T.F1a;
+            sl[5 * B.lanes] = T.F1i;
+            sl[6 * B.lanes] = T.S.tau;
+            double h;
+            const int o = traj4_step_k(P, K, T, h, kTab);
+            sl[7 * B.lanes] = h;
+            if (o == OUT_ACCEPT) ++c;
+            ++guard;
+        }
+        if (c != cnt) {      // the recomputation did not retrace the forward pass
+            A.e2 = kReplayFailed;
+            break;
+        }
+        for (int32_t s = c - 1; s >= 0; --s) {
+            const double* sl = B.scr + (int64_t)s * kScr * B.lanes + gl;
+            step_adjoint(P, L, k, inv_De, sl[0], sl[1 * B.lanes], sl[2 * B.lanes], sl[3 * B.lanes],
+                         sl[4 * B.lanes], sl[5 * B.lanes], sl[6 * B.lanes], sl[7 * B.lanes], A);
+        }
+    }
+    // adjoint at the start, parameter sums over the three axes
+    if (lane4 < 3) {
+        B.lam[(int64_t)k * P.n + i] = A.xa;
+        B.lam[(int64_t)(3 + k) * P.n + i] = A.xi;
+        B.lam[(int64_t)(6 + k) * P.n + i] = A.va;
+        B.lam[(int64_t)(9 + k) * P.n + i] = A.vi;
+    }
+    const double pq = quad_sum3(lane4 < 3 ? A.pq : 0.0), pD = quad_sum3(lane4 < 3 ? A.pD : 0.0);
+    if (lane4 == 0) {
+        B.acc[i] = pq;
+        B.acc[P.n + i] = pD;
+        B.acc[2 * P.n + i] = (double)A.e2;
+        if (A.e2 == kReplayFailed) B.info[P.n + i] = kSkip;
+    }
+}
+
 __global__ void __launch_bounds__(256) k_adj_reverse(KParams P, Work W, AdjBuf B)
 {
-    const int lane4 = __lane_id() & 3;
+    const int lane = __lane_id();
+    const int lane4 = lane & 3;
     const int k = quad_axis();
     const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 2;     // resident quad
     const int64_t gl = q * 4 + lane4;
-    if (gl >= B.lanes) return;                  // lanes beyond the scratch (quad-uniform)
+    const bool leader = lane4 == 0;
+    const uint64_t lt = (lane & ~3) == 0 ? 0ull : (~0ull >> (64 - (lane & ~3)));
     const StepK K = step_k_in_registers(P);     // latency-bound: launch constants held in registers
     const unsigned long long queued = B.ctl[1];
+    // Every lane of the wave stays in this loop until no quad of the wave has work, so the loop's
+    // exit and the queue hand-out below are wave-uniform: quads that need a trajectory take queue
+    // positions by ballot rank from one atomic of the wave.  (A per-quad exit around a lane-0 atomic
+    // and a shuffle lets the compiler run the shuffle of the three other lanes ahead of their
+    // leader's atomic, so those lanes would keep re-reading a stale position.)
+    bool need = gl < B.lanes;                   // quads beyond the scratch take no work
+    bool active = false;
+    int64_t i = -1;
     for (;;) {
-        // the quad's first lane takes the next queue position and hands it to the other three
-        unsigned long long pos = 0ull;
-        if (lane4 == 0) pos = atomicAdd(&B.ctl[0], 1ull);
-        pos = __shfl(pos, __lane_id() & ~3);
-        if (pos >= queued) break;
-        const int64_t i = B.order[pos];
-        Lane L;
-        work_lane(W, i, L);
-        TrajParams tp;
-        traj_params(P, i, tp);
-        const double inv_De = 1.0 / tp.De;
-        const int64_t m = B.off[i + 1] - B.off[i];
-        const double* R = B.rec + B.off[i] * kRec;
-        const int32_t ncom = B.info[i];
-        Adj4 A;
-        A.xa = B.lam[(int64_t)k * P.n + i];
-        A.xi = B.lam[(int64_t)(3 + k) * P.n + i];
-        A.va = B.lam[(int64_t)(6 + k) * P.n + i];
-        A.vi = B.lam[(int64_t)(9 + k) * P.n + i];
-        A.pq = A.pD = 0.0;
-        A.e2 = 0;
-        {   // the final step
-            const double* r = R + (m - 1) * kRec;
-            step_adjoint(P, L, k, inv_De, r[k * 6 + 0], r[k * 6 + 1], r[k * 6 + 2], r[k * 6 + 3], r[k * 6 + 4],
-                         r[k * 6 + 5], r[18], r[19], A);
-        }
-        for (int32_t j = ncom / kSeg; j >= 0; --j) {
-            const int32_t cnt = min(kSeg, ncom - j * kSeg);
-            if (cnt <= 0) continue;
-            // recompute the segment from its checkpoint, keeping each committed step's start
-            const double* r = R + (int64_t)j * kRec;
-            Traj4 T;
-            T.L = L;
-            scal_init(P, T.S);
-            T.xa = r[k * 6 + 0];
-            T.xi = r[k * 6 + 1];
-            T.va = r[k * 6 + 2];
-            T.vi = r[k * 6 + 3];
-            T.F1a = r[k * 6 + 4];
-            T.F1i = r[k * 6 + 5];
-            T.S.tau = r[18];
-            T.S.h = r[19];
-            T.S.nacc = 0;
-            {
-                const double dk = T.xa - T.xi, wk = T.va - T.vi;
-                const double d0 = quad_bcast<0>(dk), d1 = quad_bcast<1>(dk), d2 = quad_bcast<2>(dk);
-                const double w0 = quad_bcast<0>(wk), w1 = quad_bcast<1>(wk), w2 = quad_bcast<2>(wk);
-                T.S.rho_prev = dot3(d0, d1, d2, d0, d1, d2);
-                T.S.s_prev = dot3(d0, d1, d2, w0, w1, w2);
-            }
-            int32_t c = 0;
-            int guard = 0;
-            while (c < cnt && !T.S.done && guard < 64 * kSeg) {
-                double* sl = B.scr + (int64_t)c * kScr * B.lanes + gl;
-                sl[0 * B.lanes] = T.xa;
-                sl[1 * B.lanes] = T.xi;
-                sl[2 * B.lanes] = T.va;
-                sl[3 * B.lanes] = T.vi;
-                sl[4 * B.lanes] = T.F1a;
-                sl[5 * B.lanes] = T.F1i;
-                sl[6 * B.lanes] = T.S.tau;
-                double h;
-                const int o = traj4_step_k(P, K, T, h, kTab);
-                sl[7 * B.lanes] = h;
-                if (o == OUT_ACCEPT) ++c;
-                ++guard;
-            }
-            if (c != cnt) {      // the recomputation did not retrace the forward pass
-                A.e2 = kReplayFailed;
-                break;
-            }
-            for (int32_t s = c - 1; s >= 0; --s) {
-                const double* sl = B.scr + (int64_t)s * kScr * B.lanes + gl;
-                step_adjoint(P, L, k, inv_De, sl[0], sl[1 * B.lanes], sl[2 * B.lanes], sl[3 * B.lanes],
-                             sl[4 * B.lanes], sl[5 * B.lanes], sl[6 * B.lanes], sl[7 * B.lanes], A);
+        const uint64_t mask = __ballot(need && leader);
+        if (mask) {
+            const int first = __ffsll((unsigned long long)mask) - 1;
+            unsigned long long base = 0ull;
+            if (lane == first) base = atomicAdd(&B.ctl[0], (unsigned long long)__popcll(mask));
+            base = __shfl(base, first, 64);
+            if (need) {
+                const unsigned long long pos = base + (unsigned long long)__popcll(mask & lt);
+                active = pos < queued;
+                i = active ? B.order[pos] : -1;
+                need = false;          // a quad past the end of the queue takes no more work
             }
         }
-        // adjoint at the start, parameter sums over the three axes
-        if (lane4 < 3) {
-            B.lam[(int64_t)k * P.n + i] = A.xa;
-            B.lam[(int64_t)(3 + k) * P.n + i] = A.xi;
-            B.lam[(int64_t)(6 + k) * P.n + i] = A.va;
-            B.lam[(int64_t)(9 + k) * P.n + i] = A.vi;
-        }
-        const double pq = quad_sum3(lane4 < 3 ? A.pq : 0.0), pD = quad_sum3(lane4 < 3 ? A.pD : 0.0);
-        if (lane4 == 0) {
-            B.acc[i] = pq;
-            B.acc[P.n + i] = pD;
-            B.acc[2 * P.n + i] = (double)A.e2;
-            if (A.e2 == kReplayFailed) B.info[P.n + i] = kSkip;
+        if (!__any(active)) break;
+        if (active) {
+            reverse_trajectory(P, W, B, K, i, k, lane4, gl);
+            active = false;
+            need = true;
         }
     }
 }

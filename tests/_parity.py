@@ -110,6 +110,21 @@ PROBE_SIGNS = (np.array([1.0, -1.0, 1.0]), np.array([-1.0, 1.0, 1.0]), np.array(
                np.array([-1.0, -1.0, -1.0]))
 
 
+# Round-off probes of the oracle's tangent.  orc_tangent rebuilds the head-on start from (theta, phi, E),
+# so probes of y0 never reach it: its probes move theta and phi by one ulp each (the start state then
+# moves at round-off level, as the y0 probes of probe_spread do for the integration).
+ANGLE_PROBES = ((1.0, -1.0), (-1.0, 1.0), (1.0, 1.0), (-1.0, -1.0))
+
+
+def tangent_runs(problem, theta, phi, E, q_ratio):
+    """The oracle's tangent on its FMA twin build and at the four one-ulp angle probes: [(d, Phi, ftle)]."""
+    runs = [oracle.tangent(problem, theta, phi, E, q_ratio, twin=True)]
+    for a, b in ANGLE_PROBES:
+        runs.append(oracle.tangent(problem, theta * (1.0 + a * 2.0 ** -52), phi * (1.0 + b * 2.0 ** -52), E,
+                                   q_ratio))
+    return runs
+
+
 def _direct(res, i):
     return res[i]["n_bounce"] <= 1 and (res[i]["status"] & oracle.EXITED) != 0
 

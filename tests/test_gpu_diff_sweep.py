@@ -65,11 +65,7 @@ def test_sweep_tangent_matches_oracle_on_direct_trajectories():
         th = math.acos(d["cos_theta"])
         qr = w.system.q_ratio
         g_or, _, _ = oracle.tangent(P[j], th, d["phi"], d["E"], qr)
-        runs = [oracle.tangent(P[j], th, d["phi"], d["E"], qr, twin=True)]
-        for sg in PT.PROBE_SIGNS:
-            q = P[j].copy()
-            q["y0"][0:3] *= 1.0 + sg * 2.0 ** -52
-            runs.append(oracle.tangent(q, th, d["phi"], d["E"], qr))
+        runs = PT.tangent_runs(P[j], th, d["phi"], d["E"], qr)
         s = _scales(d)
         for k in range(3):
             b = g_or[k] * s

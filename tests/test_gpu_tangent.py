@@ -23,16 +23,12 @@ def _scales(w):
 def tangent_spread(p, th, ph, w):
     """Round-off spread of the oracle's tangent for one trajectory: the worst difference, per
     observable (norm of the parameter-scaled gradient) and for Phi (max entry), between the oracle
-    and five round-off probes of it (the FMA twin build and +-1 ulp start positions).  The tangent
+    and five round-off probes of it (the FMA twin build and +-1 ulp in theta and phi).  The tangent
     is far worse conditioned than the final state: a collision that stretches phase space by 10^3
     turns a round-off shift of the trajectory into a relative change of Phi near 1e-6."""
     s = _scales(w)
     d, Phi, _ = oracle.tangent(p, th, ph, w.system.E, w.system.q_ratio)
-    runs = [oracle.tangent(p, th, ph, w.system.E, w.system.q_ratio, twin=True)]
-    for sg in PT.PROBE_SIGNS:
-        q = p.copy()
-        q["y0"][0:3] *= 1.0 + sg * 2.0 ** -52
-        runs.append(oracle.tangent(q, th, ph, w.system.E, w.system.q_ratio))
+    runs = PT.tangent_runs(p, th, ph, w.system.E, w.system.q_ratio)
     sd = np.zeros(3)
     sp = 0.0
     for d2, P2, _ in runs:
@@ -111,11 +107,7 @@ def test_lyapunov_spectrum_matches_oracle_and_pairs():
         lo = oracle.lyapunov_spectrum(Phi, m_a, m_i, t_f)
         # the probes' spread of the oracle's spectrum, in ln s
         spread = np.zeros(12)
-        q_runs = [oracle.tangent(P[gid], th_ph[gid][0], th_ph[gid][1], w.system.E, w.system.q_ratio, twin=True)]
-        for sg in PT.PROBE_SIGNS:
-            q = P[gid].copy()
-            q["y0"][0:3] *= 1.0 + sg * 2.0 ** -52
-            q_runs.append(oracle.tangent(q, th_ph[gid][0], th_ph[gid][1], w.system.E, w.system.q_ratio))
+        q_runs = PT.tangent_runs(P[gid], th_ph[gid][0], th_ph[gid][1], w.system.E, w.system.q_ratio)
         for _, P2, _ in q_runs:
             spread = np.maximum(spread, np.abs(oracle.lyapunov_spectrum(P2, m_a, m_i, t_f) - lo) * t_f)
         ok = (lo - lo[0]) * t_f > 0.5 * np.log(1e-12)
