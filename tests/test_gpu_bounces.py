@@ -1,8 +1,12 @@
 """GPU bounce bookkeeping and bound-state bit against the oracle on starts whose answers are fixed
 by closed forms (the oracle's pins in test_oracle_bounces.py): a bound radial oscillation with six
 periapses, relative energies of -2 % and +2 % of |V| at the start, and head-on scattering, all with
-the trap off.  Same step sequence, so the bounce count, status and step counts must be identical and
-the first and last bounce times equal to rounding."""
+the trap off.  Same accept/reject decisions, so the bounce count, status and step counts must be
+identical; the first and last bounce times within max(1e-12, 10 x the oracle's round-off spread)
+relative, the spread over its FMA twin and four one-ulp probes of the start positions.  The embedded
+error estimate at rtol 1e-12 is a difference of nearly equal stage sums that keeps about seven digits,
+so round-off moves every step size by ~1e-8 while the decisions stay the same: over the six periods of
+the bound oscillation the bounce times of the oracle's probes spread by 6e-9..1.4e-8."""
 import math
 
 import numpy as np
@@ -88,7 +92,18 @@ def test_bounces_and_bound_state_match_the_oracle_on_closed_form_starts():
         assert got["n_bounce"][0] == r["n_bounce"]
         assert int(got["status"][0]) & 0xFFFF == int(r["status"])
         assert got["n_accept"][0] == r["n_accept"] and got["n_reject"][0] == r["n_reject"]
+        P = np.array([p])
+        runs = [oracle.integrate(P, twin=True)[0]]
+        for sg in PT.PROBE_SIGNS:
+            q = P.copy()
+            q["y0"][:, 0:3] *= 1.0 + sg * 2.0 ** -52
+            runs.append(oracle.integrate(q)[0])
         for gk, rk in (("t_bounce_first", "t_first"), ("t_bounce_last", "t_last")):
-            assert abs(got[gk][0] - r[rk]) <= 1e-12 * abs(r[rk]), (name, gk)
+            spread = max(abs(x[rk] - r[rk]) for x in runs)
+            bar = max(1e-12 * abs(r[rk]), 10.0 * spread)
+            print(f"{name}: {gk} |gpu - oracle| / |oracle| = {abs(got[gk][0] - r[rk]) / max(abs(r[rk]), 1e-300):.2e}, "
+                  f"spread {spread / max(abs(r[rk]), 1e-300):.2e}", flush=True)
+            assert abs(got[gk][0] - r[rk]) <= bar, (name, gk)
+            assert bar <= 1e-6 * abs(r[rk]), (name, gk)        # the bar stays meaningful
     # the cases cover what they are meant to: six bounces bound, the bit both ways
     assert [c[0] for c in cases][0] == "oscillation"
