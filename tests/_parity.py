@@ -39,6 +39,10 @@ BOUNCE_BINS = [(0, 0), (1, 1), (2, 2), (3, 4), (5, 8), (9, 16), (17, 10 ** 9)]
 # caps of the round-off-widened bar (measured on the parity workloads with the oracle's probes:
 # 0-10.6 % of direct trajectories above 1e-6, largest bar 4.8e-4, no probe leaving the direct set)
 WIDE_FRAC = 0.15
+# the linear trap (q_y = -q_x): its direct trajectories lie near the separatrix of the phi = pi/4
+# saddle, and the oracle's probes alone put 25 % (8x8 grid), 6 % (64x64 ids 1000-1776) and 33 % (the
+# first 4096 ids of 64x64) of them above 1e-6
+WIDE_FRAC_LINEAR = 0.35
 MAX_BAR = 1e-3
 DROP_FRAC = 0.02
 STEP_CEIL = 0.05
@@ -272,7 +276,7 @@ def survival_mismatches(ref, got, idx, k_se=3.0):
     return bad
 
 
-def check_parity(P, ref, got, name, min_direct=1):
+def check_parity(P, ref, got, name, min_direct=1, wide_frac=WIDE_FRAC):
     """The whole bar on one workload sample: direct trajectories one by one (capped round-off bar,
     bounce times, step counts), the rest in ensemble (including complex survival).  Returns
     (direct, rest, report)."""
@@ -289,7 +293,7 @@ def check_parity(P, ref, got, name, min_direct=1):
           f"above 1e-6, widest bar {rep['max_bar']:.1e}), {len(rest)} in ensemble, {dropped} of the oracle's "
           f"direct exits compared in ensemble", flush=True)
     assert len(direct) >= min_direct, f"{name}: only {len(direct)} direct trajectories"
-    assert rep["above_1e-6"] <= WIDE_FRAC, f"{name}: {rep['above_1e-6']:.1%} of direct bars above 1e-6"
+    assert rep["above_1e-6"] <= wide_frac, f"{name}: {rep['above_1e-6']:.1%} of direct bars above 1e-6"
     assert rep["max_bar"] <= MAX_BAR, f"{name}: widest bar {rep['max_bar']:.1e}"
     assert dropped <= max(1, int(DROP_FRAC * oracle_direct)), f"{name}: {dropped} direct exits dropped"
     bad = per_trajectory_mismatches(P, ref, got, direct, check_counts=False, spread=spread)

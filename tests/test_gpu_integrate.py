@@ -31,8 +31,8 @@ def oracle_run(w, ids):
     return P, oracle.integrate(P)
 
 
-def assert_parity(P, ref, got, name, min_direct=1):
-    direct, rest, _ = PT.check_parity(P, ref, got, name, min_direct=min_direct)
+def assert_parity(P, ref, got, name, min_direct=1, wide_frac=PT.WIDE_FRAC):
+    direct, rest, _ = PT.check_parity(P, ref, got, name, min_direct=min_direct, wide_frac=wide_frac)
     return direct, rest
 
 
@@ -293,4 +293,4 @@ def test_linear_trap_parity(kernel):
         got = run(w, n=n, id0=id0, kernel=kernel)
         P, ref = oracle_run(w, np.arange(id0, id0 + n))
         assert np.all(P["q"][:, 1] == -P["q"][:, 0]) and np.all(P["q"][:, 2] == 0.0)
-        assert_parity(P, ref, got, f"linear{side}/{kernel}", min_direct=min_direct)
+        assert_parity(P, ref, got, f"linear{side}/{kernel}", min_direct=min_direct, wide_frac=PT.WIDE_FRAC_LINEAR)
