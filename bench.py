@@ -2,11 +2,15 @@
 plain one-launch-per-batch kernel, FP64 at rtol 1e-10, with the achieved fraction of the MI355X
 FP64 vector peak and the CPU oracle timed on the host as a baseline.
 
-One "step" = one iat_integrate call over the whole workload (every trajectory integrated from
-its start to its exit or t_max, observables written).  Inputs are generated on the device from
-trajectory ids, so nothing crosses PCIe inside the timed region.
+Default workload: the 1e8-trajectory streaming sweep (Yb+ with Li6, K40 and Cs133, E log-uniform over
+1 uK - 1 mK, q_x uniform over 0.05 - 0.35, De log-uniform over 0.01 - 100 K), keeping only on-device
+histograms.  One "step" = one chunk of 2^22 ids of that stream: the K timed chunks (after W warm-up
+chunks) are integrated as one batch by one iat_integrate call, whose refill queue runs over all of
+them, and reduced to the W0 and heating histograms on the device.  Other workloads: one step = one
+iat_integrate call over the whole workload.  Inputs are generated on the device from trajectory ids,
+so nothing crosses PCIe inside the timed region.
 
-    python bench.py [--steps K] [--warmup W] [--workload grid1024|grid8|sweep|stream|thermal|fig4|tangent|adjoint]
+    python bench.py [--steps K] [--warmup W] [--workload stream|grid1024|grid8|sweep|thermal|fig4|tangent|adjoint]
 """
 from __future__ import annotations
 
@@ -30,13 +34,16 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 20 chunks for stream, 3 passes otherwise)")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="grid1024",
-                    choices=["grid1024", "grid8", "sweep", "stream", "thermal", "fig4", "tangent", "adjoint"],
-                    help="grid1024: the 1024^2 head-on grid (one batch); sweep: the 1.2e7-trajectory 225-cell "
-                         "sweep with per-cell reductions; stream: the 1e8-trajectory Li/K/Cs sweep keeping only "
-                         "histograms (both in chunks over several streams); tangent / adjoint: the 512^2 "
+    ap.add_argument("--workload", default="stream",
+                    choices=["grid1024", "grid8", "sweep", "stream", "stream-chunks", "thermal", "fig4", "tangent",
+                             "adjoint"],
+                    help="stream (default): the 1e8-trajectory Li/K/Cs sweep keeping only histograms, one step = "
+                         "one 2^22-id chunk; stream-chunks: the same workload in chunks over several streams, one "
+                         "step = the whole 1e8; grid1024: the 1024^2 head-on grid (one batch); sweep: the "
+                         "1.2e7-trajectory 225-cell sweep with per-cell reductions; tangent / adjoint: the 512^2 "
                          "differentiation grid")
     ap.add_argument("--autotune", default="", metavar="CACHE.json",
                     help="pick block / refill / step budget by timing candidates on 2^16 ids (cached)")
@@ -71,7 +78,8 @@ def parse():
 def workload(name):
     import workloads as W
     return {"grid1024": W.config2, "grid8": W.config1, "sweep": W.config3, "stream": W.config5,
-            "thermal": W.fig3_thermal, "fig4": W.fig4_energy, "tangent": W.config4, "adjoint": W.config4}[name]()
+            "stream-chunks": W.config5, "thermal": W.fig3_thermal, "fig4": W.fig4_energy, "tangent": W.config4,
+            "adjoint": W.config4}[name]()
 
 
 # algorithmic FLOP of the differentiation (same canonical count as FLOP_PER_RHS): per attempted step of the
@@ -150,7 +158,8 @@ def chunked_job(api, torch, w, n, args, stats, kernel):
 
     res = api.run_chunks(w, n=n, chunk=chunk, n_streams=args.streams, kernel=kernel,
                          cells=args.workload in ("sweep", "thermal"),
-                         hist=args.workload in ("stream", "fig4"), stats=stats, progress=progress)
+                         hist=args.workload in ("stream", "stream-chunks", "fig4"), stats=stats,
+                         progress=progress)
     e1.record(cur)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / 1e3, res, chunk
@@ -235,6 +244,149 @@ def main_chunked(args):
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w.with_n(n), args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+STREAM_CHUNK = 1 << 22
+
+
+def main_stream(args):
+    """The 1e8-trajectory Li/K/Cs stream, one step = one chunk of STREAM_CHUNK ids.  The W warm-up chunks
+    (ids [0, W C)) and then the K timed chunks (ids [W C, (W + K) C)) are each integrated as one batch by
+    one iat_integrate call (persistent refill over the whole batch; long-lived complexes continue in the
+    four-lane tail and the solo level) and reduced on the device to the W0 and heating histograms; only
+    those are kept.  Timed with HIP events on the launch stream, bracketed by device synchronisation."""
+    import torch
+    from paper_2509_15117_amd import api
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    w = workload("stream")
+    C = args.chunk or STREAM_CHUNK
+    K, Wu = args.steps, args.warmup
+    sp = w.species()
+    cur = torch.cuda.current_stream()
+
+    def batch(n, id0, out, hist, **kw):
+        api.integrate(w.system, sp, w.gen, n, id0=id0, out=out, counters=False, **kw)
+        api.reduce_hist(w.system, sp, w.gen, n, out, id0=id0, out=hist)
+
+    n = K * C
+    id0 = Wu * C
+    out = api.alloc_obs(n, dev, counters=False)
+    if Wu > 0:
+        m = Wu * C
+        print(f"[bench] stream warm-up: {Wu} chunks ({m} ids)", file=sys.stderr, flush=True)
+        wo = {k: v[:m] for k, v in out.items()} if m <= n else api.alloc_obs(m, dev, counters=False)
+        batch(m, 0, wo, None)
+        del wo
+    torch.cuda.synchronize()
+    hist = torch.zeros(len(w.gen.species) * 2 * 64 + 256, dtype=torch.float64, device=dev)
+    stats = api.new_stats()
+    ms = api.phase_ms()
+    torch.cuda.synchronize()
+    print(f"[bench] stream: {K} chunks of {C} ids (ids {id0} .. {id0 + n - 1}) as one batch", file=sys.stderr,
+          flush=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(cur)
+    batch(n, id0, out, hist, stats=stats, kernel_ms=ms)
+    e1.record(cur)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    secs = e0.elapsed_time(e1) / 1e3
+    s = stats.cpu().tolist()
+    steps_max, gid_max = api.longest_of(stats.cpu())
+    print(f"[bench] stream: {secs:.2f} s ({n / secs:.0f} trajectories/s), phases ms "
+          f"{[round(x, 1) for x in ms]}, longest trajectory {gid_max} with {steps_max} attempted steps",
+          file=sys.stderr, flush=True)
+    kernels = []
+    for name, ph, rhs in (("k_integrate_persistent", 1, s[0] - s[6] - s[8]), ("k_integrate_tail", 2, s[6]),
+                          ("k_integrate_solo", 3, s[8])):
+        secs_k = ms[ph] / 1e3
+        if secs_k > 0:
+            tf = FLOP_PER_RHS * rhs / secs_k / 1e12
+            kernels.append({"kernel": name, "avg_launch_ms": secs_k * 1e3, "rhs_per_launch": rhs,
+                            "flop_per_launch": FLOP_PER_RHS * rhs, "achieved": tf, "frac": tf / FP64_PEAK_TFLOPS,
+                            "traffic": traffic_bytes(args.traffic_file, w.name, name),
+                            "launch": f"one launch over the {n} ids of the timed batch"})
+    dom = max(kernels, key=lambda k: k["avg_launch_ms"])
+    h = api.split_hist(hist)[0].cpu()
+    p_cx = [float(h[k, :, 1].sum() / max(h[k, :, 0].sum(), 1.0)) for k in range(h.shape[0])]
+    out_line = {
+        "metric": "trajectories/s + RK stages/s (FP64, rtol 1e-10): refill kernel vs plain, % FP64 peak",
+        "value": n / secs, "unit": "trajectories/s", "n_gpus": 1, "steps": K, "warmup": Wu,
+        "ms_per_step": secs * 1e3 / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "trajectories_in_stream": w.n, "chunk": C, "timed_ids": [id0, id0 + n],
+                   "step": "one chunk of 2^22 ids; the K timed chunks integrated as one batch (one refill queue) "
+                           "and reduced to on-device histograms", "kernel": "persistent",
+                   "rtol": w.system.rtol, "atol": w.system.atol, "max_steps": w.system.max_steps,
+                   "reductions": "W0 (complex/total over log10(E/W0), per species) and heating histograms"},
+        "rk_stages_per_s": s[0] / secs, "accepted_steps_per_s": s[1] / secs,
+        "fp64_frac_peak": FLOP_PER_RHS * s[0] / secs / (FP64_PEAK_TFLOPS * 1e12),
+        "active_lane_fraction": s[5] / max(s[4], 1),
+        "roofline": {"bound": "alu", "kernel": dom["kernel"], "achieved": dom["achieved"], "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": dom["frac"], "traffic": dom["traffic"],
+                     "avg_launch_ms": dom["avg_launch_ms"], "flop_per_launch": dom["flop_per_launch"]},
+        "kernels": kernels,
+        "phases_ms": {"setup": ms[0], "main": ms[1], "tail": ms[2], "solo": ms[3], "observe": ms[4]},
+        "reduce_ms": secs * 1e3 - sum(ms),
+        "tail_trajectories": s[7] + s[9], "solo_trajectories": s[9],
+        "longest_trajectory": {"id": gid_max, "attempted_steps": steps_max},
+        "p_complex_by_species": dict(zip(w.species_names, p_cx)),
+        "host_wall_s": wall,
+    }
+    if not args.no_critical_path and steps_max > 0:
+        out_line["critical_path"] = stream_critical_path(api, torch, w, gid_max, steps_max, ms[2] + ms[3])
+    if not args.no_plain:
+        # refill against plain on one matched chunk: the first timed chunk, each kernel in one call
+        res = {}
+        for kern in ("plain", "persistent"):
+            o = {k: v[:C] for k, v in out.items()}
+            st = api.new_stats()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(cur)
+            api.integrate(w.system, sp, w.gen, C, id0=id0, out=o, counters=False, kernel=kern, stats=st)
+            b.record(cur)
+            torch.cuda.synchronize()
+            t = a.elapsed_time(b) / 1e3
+            sk = st.cpu().tolist()
+            res[kern] = {"trajectories_per_s": C / t, "rk_stages_per_s": sk[0] / t, "seconds": t,
+                         "fp64_frac_peak": FLOP_PER_RHS * sk[0] / t / (FP64_PEAK_TFLOPS * 1e12),
+                         "active_lane_fraction": sk[5] / max(sk[4], 1)}
+            print(f"[bench] matched chunk ({C} ids from {id0}), {kern}: {t:.2f} s", file=sys.stderr, flush=True)
+        out_line["plain"] = dict(res["plain"], sample=f"one chunk of {C} ids from id {id0}")
+        out_line["refill_same_chunk"] = res["persistent"]
+        out_line["speedup_vs_plain"] = res["plain"]["seconds"] / res["persistent"]["seconds"]
+    pk = api.fp64_peak()
+    out_line["fp64_peak_measured_tflops"] = pk
+    out_line["roofline"]["frac_of_measured_peak"] = out_line["roofline"]["achieved"] / pk
+    if not args.no_cpu:
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        out_line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out_line), flush=True)
+
+
+def stream_critical_path(api, torch, w, gid, steps, tail_ms, cap=400_000):
+    """The batch cannot end before its longest trajectory (found by the call's stats) has run its steps
+    one after another.  A bounded prefix of that trajectory timed alone in the solo kernel gives the
+    per-step latency; bound = its attempted steps x that latency, frac = bound / the tail phases."""
+    import copy
+    wl = copy.deepcopy(w)
+    wl.system.max_steps = cap
+    ms = api.phase_ms()
+    r = api.integrate_workload(wl, n=1, id0=gid, counters=True, kernel="persistent", step_budget=1, tail_budget=1,
+                               kernel_ms=ms)
+    s1 = int(r["n_accept"].item() + r["n_reject"].item()) - 2
+    us = ms[3] * 1e3 / max(s1, 1)
+    bound_ms = steps * us / 1e3
+    print(f"[bench] longest trajectory {gid}: {steps} attempted steps, {us:.3f} us per step alone", file=sys.stderr,
+          flush=True)
+    return {"trajectory_id": gid, "attempted_steps": steps, "lone_us_per_step": us, "lone_sample_steps": s1,
+            "bound_ms": bound_ms, "tail_ms": tail_ms, "frac_of_tail": bound_ms / tail_ms if tail_ms > 0 else None}
 
 
 def pipelined(api, torch, w, passes, launch):
@@ -461,6 +613,8 @@ def lone_latency(args):
 
 def main():
     args = parse()
+    if args.steps is None:
+        args.steps = 20 if args.workload == "stream" else 3
     if args.latency >= 0:
         return lone_latency(args)
     if args.compare_solo > 0:
@@ -474,7 +628,13 @@ def main():
                               "n_gpus": args.gpus}))
             sys.exit(2)
         return main_diff(args)
-    if args.workload in ("sweep", "stream", "thermal", "fig4"):
+    if args.workload == "stream":
+        if args.gpus != 1:
+            print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",
+                              "n_gpus": args.gpus}))
+            sys.exit(2)
+        return main_stream(args)
+    if args.workload in ("sweep", "stream-chunks", "thermal", "fig4"):
         if args.gpus != 1:
             print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",
                               "n_gpus": args.gpus}))

@@ -161,13 +161,16 @@ enum { IAT_KERNEL_PLAIN = 1, IAT_KERNEL_PERSISTENT = 2 };
  * outlive step_budget continue four lanes per trajectory in a second kernel, and those that
  * outlive tail_budget there finish in a third, one trajectory per wave.  All kernels give the
  * same bits for the same trajectory.
- * Zero fields take defaults.  stats, if not NULL, is a device uint64[10] to which the
+ * Zero fields take defaults.  stats, if not NULL, is a device uint64[11] to which the
  * call ADDS: [0] RHS evaluations, [1] accepted steps, [2] rejected steps,
  * [3] trajectories finished, [4] issued step slots (one-lane kernels: wave iterations x 64;
  * four-lane kernels: wave iterations x trajectories per wave), [5] useful step slots (attempted
  * steps), [6] RHS evaluations performed inside the four-lane tail kernel, [7] trajectories
  * finished by it, [8] RHS evaluations performed inside the one-per-wave solo kernel,
- * [9] trajectories finished by it.
+ * [9] trajectories finished by it; and whose [10] it raises (atomic max) to
+ * (attempted steps << 34) | global id of the longest trajectory the call finished (attempted steps
+ * = accepted + rejected, clamped to 2^30 - 1; the global id is gen.id0 + index for GRID, SWEEP and
+ * THERMAL batches and the index for ARRAYS batches, modulo 2^34): the batch's critical path.
  * kernel_ms, if not NULL, is HOST float[5] that receives the durations of the call's phases on
  * its stream (setup, main integration kernel, four-lane tail kernel, solo kernel, observables),
  * measured with HIP events; the call then waits for its work to finish before returning. */
@@ -201,7 +204,7 @@ int iat_integrate(const iat_system* sys, const iat_species* species /* host */, 
                   void* ckpt_ws, size_t ckpt_bytes, void* stream);
 
 /* Reductions of a batch's outputs (the ensemble quantities of Figs. 3 and 4, and the fractal
- * structure of Fig. 1).  obs needs dE_ion, n_bounce and status.  out is device memory; CELLS, W0_HIST and
+ * structure of Fig. 1).  obs needs dE_ion, n_bounce and status.  out is device memory; CELLS, both W0 histograms and
  * the LIFETIME counts ADD to it (zero it first to start), so chunks of one sweep accumulate;
  * BOXCOUNT overwrites it.
  * IAT_REDUCE_CELLS (SWEEP batches): per cell c (cell = id mod n_cells), out[5c..5c+4] =
@@ -210,6 +213,9 @@ int iat_integrate(const iat_system* sys, const iat_species* species /* host */, 
  *   log10(E/W0) over [-3, 3] (clamped), out[(s*64 + b)*2 + {0,1}] = (total, complex) counts, W0 from
  *   Eq. (2) with omega = (Omega/2) sqrt(a_x + q_x^2/2); then out[n_slots*128 + b], b < 256: counts of
  *   sign(dE) log10(1 + |dE|/(k_B 1 nK)) over +-log10(1 + 1e8) (clamped).
+ * IAT_REDUCE_W0_HIST_BOUND: as W0_HIST, with out[(s*64 + b)*2 + 1] counting the trajectories that
+ *   reached the negative-energy bound state (IAT_ST_BOUND_SEEN; the temporary atom-ion bound state of
+ *   the Eq. (2) text) instead of IAT_ST_COMPLEX.
  * IAT_REDUCE_BOXCOUNT (a whole square power-of-two GRID batch): box-counting dimensions of the
  *   complex-forming set.  For boxes of s = 2^k cells, N_set(k) = boxes holding a complex cell and
  *   N_bnd(k) = boxes holding both kinds; out[0] = D_boundary, out[1] = D_set (least-squares slopes
@@ -227,6 +233,7 @@ int iat_integrate(const iat_system* sys, const iat_species* species /* host */, 
 #define IAT_REDUCE_W0_HIST 2
 #define IAT_REDUCE_BOXCOUNT 3
 #define IAT_REDUCE_LIFETIME 4
+#define IAT_REDUCE_W0_HIST_BOUND 5
 int iat_reduce(const iat_system* sys, const iat_species* species, int n_species,
                const iat_batch* batch, const iat_obs* obs, int kind, double* out, void* stream);
 

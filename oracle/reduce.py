@@ -94,9 +94,12 @@ def sweep_params(ids, workload):
     return E, q, slot, sp
 
 
-def w0_hist(ids, workload, dE, status):
-    """Returns (hist (n_slots, 64, 2) of (total, complex), heat (256,), w0 coordinate, heat coordinate)
-    for a sweep workload; the coordinates let a comparison recognise values that sit on a bin edge."""
+def w0_hist(ids, workload, dE, status, flag=None):
+    """Returns (hist (n_slots, 64, 2) of (total, flagged), heat (256,), w0 coordinate, heat coordinate)
+    for a sweep workload; the coordinates let a comparison recognise values that sit on a bin edge.
+    flag: the status bit counted in the second column, the complex flag by default (BOUND_SEEN: the
+    negative-energy bound state of the Eq. (2) text)."""
+    flag = oracle.COMPLEX if flag is None else flag
     sysw = workload.system
     spec = workload.species()
     if workload.gen.kind in ("sweep", "thermal"):      # thermal runs: E is the bath energy k_B T
@@ -114,7 +117,7 @@ def w0_hist(ids, workload, dE, status):
     cw = w0_coordinate(E, W0)
     b = _bin(cw, W0_BINS)
     hist = np.zeros((n_slots, W0_BINS, 2))
-    cpx = (np.asarray(status) & oracle.COMPLEX) != 0
+    cpx = (np.asarray(status) & flag) != 0
     np.add.at(hist, (slot, b, 0), 1.0)
     np.add.at(hist, (slot[cpx], b[cpx], 1), 1.0)
     ch = heat_coordinate(dE)

@@ -12,10 +12,10 @@ ST_COMPLEX, ST_BOUND_SEEN, ST_EXITED = 1 << 0, 1 << 1, 1 << 2
 ST_TMAX, ST_H_UNDERFLOW, ST_NONFINITE, ST_MAX_STEPS = 1 << 8, 1 << 9, 1 << 10, 1 << 11
 ST_R_UNDERFLOW, ST_WARN_R0, ST_ADJ_SKIPPED = 1 << 12, 1 << 13, 1 << 14
 MAX_SPECIES = 8
-N_STATS, N_PHASES = 10, 5
+N_STATS, N_PHASES = 11, 5
 GEN_ARRAYS, GEN_GRID, GEN_SWEEP, GEN_THERMAL = 0, 1, 2, 3
 KERNEL_PLAIN, KERNEL_PERSISTENT = 1, 2
-REDUCE_CELLS, REDUCE_W0_HIST, REDUCE_BOXCOUNT, REDUCE_LIFETIME = 1, 2, 3, 4
+REDUCE_CELLS, REDUCE_W0_HIST, REDUCE_BOXCOUNT, REDUCE_LIFETIME, REDUCE_W0_HIST_BOUND = 1, 2, 3, 4, 5
 W0_BINS, HEAT_BINS, LIFE_BINS, LIFE_SLOT = 64, 256, 96, 98
 
 EXPORTS = ["iat_integrate", "iat_integrate_tangent", "iat_adjoint", "iat_reduce", "iat_adjoint_workspace_bytes",

@@ -113,7 +113,7 @@ def batch_struct(n: int, gen, arrays: Optional[Dict[str, torch.Tensor]] = None,
 def launch_struct(kernel="persistent", block=0, blocks_per_cu=0, refill_every=0, step_budget=0,
                   stats: Optional[torch.Tensor] = None, kernel_ms=None, max_suspended=0,
                   tail_budget=0) -> _abi.Launch:
-    """stats: optional device int64 tensor of at least 10 counters; kernel_ms: optional host
+    """stats: optional device int64 tensor of at least 11 counters; kernel_ms: optional host
     ctypes float[5] for the phase durations (the call then waits).  Both are checked for size here,
     since the library writes all of their entries."""
     if stats is not None and (stats.numel() < _abi.N_STATS or stats.dtype != torch.int64 or not stats.is_cuda
@@ -142,13 +142,20 @@ def new_stats(device=None) -> torch.Tensor:
     return torch.zeros(_abi.N_STATS, dtype=torch.int64, device=device or "cuda")
 
 
+def longest_of(stats) -> tuple:
+    """(attempted steps, global id) of the longest trajectory recorded in stats[10] (0, 0 if none)."""
+    v = int(stats[10]) & 0xFFFFFFFFFFFFFFFF
+    return v >> 34, v & ((1 << 34) - 1)
+
+
 def integrate(system, species, gen, n: int, *, arrays=None, y0=None, id0=None, kernel="persistent", block=0,
               blocks_per_cu=0, refill_every=0, step_budget=0, y_final=False, counters=True, stats=None, out=None,
               stream=None, device=None, kernel_ms=None, max_suspended=0, tail_budget=0) -> Dict[str, torch.Tensor]:
     """Integrate n trajectories on the current GPU; returns device tensors of the observables.
 
     system / gen: objects with the fields of workloads.System / workloads.Generator.
-    species: [(m_atom, C4)] in atomic units.  stats: optional uint64[10] device counters (new_stats()).
+    species: [(m_atom, C4)] in atomic units.  stats: optional uint64[11] device counters (new_stats();
+    entry 10 packs the call's longest trajectory, see longest_of()).
     kernel_ms: optional phase_ms() buffer receiving the phase durations (setup, main, tail, solo,
     observables) measured with HIP events on the stream; the call then waits for completion."""
     L = _abi.load()
@@ -229,14 +236,17 @@ def reduce_cells(system, species, gen, n, obs, *, id0=None, arrays=None, out=Non
     return _reduce(_abi.REDUCE_CELLS, system, species, gen, n, obs, out, id0, arrays, stream)
 
 
-def reduce_hist(system, species, gen, n, obs, *, id0=None, arrays=None, out=None, stream=None):
+def reduce_hist(system, species, gen, n, obs, *, id0=None, arrays=None, out=None, stream=None, flag="complex"):
     """Complex/total counts over log10(E/W0) per species slot (n_slots x 64 x 2) and the heating histogram
-    (256,) in one flat tensor; use split_hist() to view them.  Passing the previous out accumulates."""
+    (256,) in one flat tensor; use split_hist() to view them.  Passing the previous out accumulates.
+    flag="bound" counts the trajectories that reached the negative-energy bound state in the second
+    column instead of the complex flag."""
     dev = obs["status"].device
     slots = len(gen.species) if gen.kind in ("sweep", "thermal") else 1
     if out is None:
         out = torch.zeros(slots * 2 * _abi.W0_BINS + _abi.HEAT_BINS, dtype=torch.float64, device=dev)
-    return _reduce(_abi.REDUCE_W0_HIST, system, species, gen, n, obs, out, id0, arrays, stream)
+    kind = {"complex": _abi.REDUCE_W0_HIST, "bound": _abi.REDUCE_W0_HIST_BOUND}[flag]
+    return _reduce(kind, system, species, gen, n, obs, out, id0, arrays, stream)
 
 
 def split_hist(flat: torch.Tensor):
@@ -343,11 +353,12 @@ class ScatteringObservables(torch.autograd.Function):
 
 
 def run_chunks(w, *, n: Optional[int] = None, chunk: int = 1 << 22, n_streams: int = 4, kernel="persistent",
-               cells: bool = False, hist: bool = False, stats: Optional[torch.Tensor] = None, progress=None,
-               sample=None, **launch):
+               cells: bool = False, hist: bool = False, hist_bound: bool = False,
+               stats: Optional[torch.Tensor] = None, progress=None, sample=None, **launch):
     """Integrate ids [0, n) of a workloads.Workload in chunks of `chunk` ids spread round-robin over
     `n_streams` streams (default priority), reducing each chunk on its stream: per-cell sums (cells=True,
-    sweeps) and the W0 / heating histograms (hist=True).  Only the reductions are kept.  While one
+    sweeps), the W0 / heating histograms (hist=True) and the W0 histogram of the bound-state flag
+    (hist_bound=True, res['hist_bound']).  Only the reductions are kept.  While one
     chunk's long-lived complexes finish in its tail kernel, the next chunks run on the other streams.
     Returns {'cells': (n_cells, 5), 'hist': flat histogram} (device tensors, summed over streams).
     progress(c, n_chunks): called on the host as chunk c completes (in chunk order).
@@ -371,6 +382,8 @@ def run_chunks(w, *, n: Optional[int] = None, chunk: int = 1 << 22, n_streams: i
     c_out = [torch.zeros(n_cells(w.gen), 5, dtype=torch.float64, device=dev) for _ in streams] if cells else None
     h_out = ([torch.zeros(slots * 2 * _abi.W0_BINS + _abi.HEAT_BINS, dtype=torch.float64, device=dev)
               for _ in streams] if hist else None)
+    hb_out = ([torch.zeros(slots * 2 * _abi.W0_BINS + _abi.HEAT_BINS, dtype=torch.float64, device=dev)
+               for _ in streams] if hist_bound else None)
     for s in streams:
         s.wait_stream(cur)
     done = []
@@ -384,6 +397,9 @@ def run_chunks(w, *, n: Optional[int] = None, chunk: int = 1 << 22, n_streams: i
             reduce_cells(w.system, w.species(), w.gen, cnt, obs, id0=id0, out=c_out[k], stream=streams[k])
         if hist:
             reduce_hist(w.system, w.species(), w.gen, cnt, obs, id0=id0, out=h_out[k], stream=streams[k])
+        if hist_bound:
+            reduce_hist(w.system, w.species(), w.gen, cnt, obs, id0=id0, out=hb_out[k], stream=streams[k],
+                        flag="bound")
         if want:
             a = int(torch.searchsorted(ids_h, torch.tensor(id0)))
             b = int(torch.searchsorted(ids_h, torch.tensor(id0 + cnt)))
@@ -409,6 +425,8 @@ def run_chunks(w, *, n: Optional[int] = None, chunk: int = 1 << 22, n_streams: i
         res["cells"] = torch.stack(c_out).sum(0)
     if hist:
         res["hist"] = torch.stack(h_out).sum(0)
+    if hist_bound:
+        res["hist_bound"] = torch.stack(hb_out).sum(0)
     if want:
         res["sample"] = s_out
         for v in s_out.values():

@@ -44,13 +44,24 @@ __device__ __forceinline__ uint64_t wave_max(uint64_t v)
 
 struct LaneStats {
     uint64_t rhs = 0, acc = 0, rej = 0, done = 0, useful = 0;
+    uint64_t longest = 0;     // (attempted steps << 34) | global id of the longest trajectory finished
 };
+
+// The longest trajectory of a call, packed so that one atomic max keeps it: attempted steps (clamped
+// to 30 bits) above the trajectory's global id (34 bits; generated batches number from gen.id0).
+__device__ __forceinline__ uint64_t longest_key(const KParams& P, int64_t i, int32_t nacc, int32_t nrej)
+{
+    int64_t steps = (int64_t)nacc + (int64_t)nrej;
+    steps = steps < 0 ? 0 : (steps > 0x3fffffff ? 0x3fffffff : steps);
+    const int64_t gid = (P.gen.kind == IAT_GEN_ARRAYS ? 0 : P.gen.id0) + i;
+    return ((uint64_t)steps << 34) | ((uint64_t)gid & 0x3ffffffffull);
+}
 
 __device__ __forceinline__ void flush_stats(uint64_t* stats, const LaneStats& s, uint64_t issued)
 {
     if (!stats) return;
     const uint64_t r = wave_sum(s.rhs), a = wave_sum(s.acc), j = wave_sum(s.rej), d = wave_sum(s.done),
-                   u = wave_sum(s.useful);
+                   u = wave_sum(s.useful), lg = wave_max(s.longest);
     if (__lane_id() == 0) {
         atomicAdd((unsigned long long*)&stats[0], (unsigned long long)r);
         atomicAdd((unsigned long long*)&stats[1], (unsigned long long)a);
@@ -58,6 +69,7 @@ __device__ __forceinline__ void flush_stats(uint64_t* stats, const LaneStats& s,
         atomicAdd((unsigned long long*)&stats[3], (unsigned long long)d);
         atomicAdd((unsigned long long*)&stats[4], (unsigned long long)issued);
         atomicAdd((unsigned long long*)&stats[5], (unsigned long long)u);
+        if (lg) atomicMax((unsigned long long*)&stats[10], (unsigned long long)lg);
     }
 }
 
@@ -92,6 +104,7 @@ __global__ void __launch_bounds__(256) k_integrate_plain(KParams P, Work W)
         st.rej = T.S.nrej;
         st.done = 1;
         st.useful = T.S.nacc + T.S.nrej;
+        if (P.stats) st.longest = longest_key(P, i, T.S.nacc, T.S.nrej);
     }
     // every lane of the wave is issued for as many steps as its slowest lane needed
     flush_stats(P.stats, st, 64ull * wave_max(iters));
@@ -138,6 +151,10 @@ __global__ void __launch_bounds__(256) k_integrate_persistent(KParams P, Work W,
                 st.rej += T.S.nrej;
                 st.done += 1;
                 st.useful += T.S.nacc + T.S.nrej;
+                if (P.stats) {
+                    const uint64_t key = longest_key(P, i, T.S.nacc, T.S.nrej);
+                    st.longest = key > st.longest ? key : st.longest;
+                }
                 active = false;
                 need = true;
             } else if (may_suspend && T.S.nacc + T.S.nrej >= P.budget) {
@@ -213,6 +230,10 @@ __device__ __forceinline__ void tail_run(const KParams& P, const Work& W, const 
                 st.useful += T.S.nacc + T.S.nrej - resumed_at;
                 tail_rhs += (uint64_t)(T.S.nrhs - resumed_rhs);
                 tail_done += 1;
+                if (P.stats) {
+                    const uint64_t key = longest_key(P, i, T.S.nacc, T.S.nrej);
+                    st.longest = key > st.longest ? key : st.longest;
+                }
             }
             active = false;
             need = (lane >> 2) < QUADS;

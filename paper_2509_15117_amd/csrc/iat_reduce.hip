@@ -6,6 +6,8 @@
 // W0_HIST   : per species, 64 bins of log10(E/W0) over [-3, 3] (total, complex), W0 from Eq. (2)
 //             with omega = (Omega/2) sqrt(a_x + q_x^2/2); and 256 bins of the heating
 //             sign(dE) log10(1 + |dE|/(k_B 1 nK)).  Integer counts accumulate exactly.
+//             W0_HIST_BOUND: the same with the second column counting trajectories that reached the
+//             negative-energy bound state (Eq. (2) text) instead of the complex flag.
 // BOXCOUNT  : box-counting dimensions of the complex-forming set of a GRID batch: for box sizes
 //             s = 2^k, the number of boxes holding complex cells (occupied) and holding both kinds
 //             (boundary); slopes of log N(s) against log(1/s) by least squares.
@@ -91,7 +93,7 @@ __device__ __forceinline__ double w0_eq2(double m_a, double m_i, double C4, doub
            cbrt(m_i * m_i * om2 * om2 * C4 / (q_x * q_x));
 }
 
-__global__ void __launch_bounds__(256) k_reduce_hist(KParams P, RedIn R, double* out, int nsp)
+__global__ void __launch_bounds__(256) k_reduce_hist(KParams P, RedIn R, double* out, int nsp, uint32_t cmask)
 {
     __shared__ double hw[IAT_MAX_SPECIES * 64 * 2];
     __shared__ double hh[256];
@@ -113,7 +115,7 @@ __global__ void __launch_bounds__(256) k_reduce_hist(KParams P, RedIn R, double*
             slot = (s < P.gen.n_species && P.gen.species[s] == tp.sp) ? s : slot;
         if (P.gen.kind != IAT_GEN_SWEEP && P.gen.kind != IAT_GEN_THERMAL) slot = 0;
         atomicAdd(&hw[(slot * 64 + b) * 2 + 0], 1.0);
-        if (R.status[i] & IAT_ST_COMPLEX) atomicAdd(&hw[(slot * 64 + b) * 2 + 1], 1.0);
+        if (R.status[i] & cmask) atomicAdd(&hw[(slot * 64 + b) * 2 + 1], 1.0);
         const double e = R.dE[i];
         const double x = (e < 0.0 ? -1.0 : 1.0) * log10(1.0 + fabs(e) / kNanoKelvin);
         int hb = (int)floor((x + X) / (2.0 * X) * 256.0);
@@ -290,10 +292,11 @@ extern "C" int iat_reduce(const iat_system* sys, const iat_species* species, int
         hipLaunchKernelGGL(k_reduce_cells_final, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, st,
                            (const double*)part, ncell, out);
         if (hipFreeAsync(part, st) != hipSuccess) return set_error(IAT_EHIP, "hipFreeAsync failed");
-    } else if (kind == IAT_REDUCE_W0_HIST) {
+    } else if (kind == IAT_REDUCE_W0_HIST || kind == IAT_REDUCE_W0_HIST_BOUND) {
         const int nsp = (batch->gen.kind == IAT_GEN_SWEEP || batch->gen.kind == IAT_GEN_THERMAL) ? batch->gen.n_species : 1;
         const int64_t blocks = std::min<int64_t>((batch->n + 255) / 256, 4096);
-        hipLaunchKernelGGL(k_reduce_hist, dim3((unsigned)blocks), dim3(256), 0, st, P, R, out, nsp);
+        const uint32_t cmask = kind == IAT_REDUCE_W0_HIST ? IAT_ST_COMPLEX : IAT_ST_BOUND_SEEN;
+        hipLaunchKernelGGL(k_reduce_hist, dim3((unsigned)blocks), dim3(256), 0, st, P, R, out, nsp, cmask);
     } else if (kind == IAT_REDUCE_LIFETIME) {
         if (!obs->t_bounce_first || !obs->t_bounce_last)
             return set_error(IAT_EINVAL, "reduce LIFETIME needs obs.t_bounce_first and obs.t_bounce_last");

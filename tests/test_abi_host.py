@@ -140,19 +140,20 @@ def test_derivatives_reject_thermal_and_explicit_starts_without_gpu():
 
 
 def test_launch_buffers_are_size_checked_before_the_call():
-    """The library writes all 10 counters of launch.stats (device) and all 5 phase durations of
+    """The library writes all 11 entries of launch.stats (device) and all 5 phase durations of
     launch.kernel_ms (host); the binding refuses smaller or misplaced buffers before any call."""
     torch = pytest.importorskip("torch")
     from paper_2509_15117_amd import api
-    assert (_abi.N_STATS, _abi.N_PHASES) == (10, 5)
+    assert (_abi.N_STATS, _abi.N_PHASES) == (11, 5)
     txt = open(os.path.join(ROOT, "include", "iat.h")).read()
-    assert "device uint64[10]" in txt and "HOST float[5]" in txt
+    assert "device uint64[11]" in txt and "HOST float[5]" in txt
     with pytest.raises(ValueError, match="stats"):
-        api.launch_struct(stats=torch.zeros(8, dtype=torch.int64))          # too short (and on the host)
+        api.launch_struct(stats=torch.zeros(10, dtype=torch.int64))         # too short (and on the host)
     with pytest.raises(ValueError, match="stats"):
-        api.launch_struct(stats=torch.zeros(10, dtype=torch.int64))         # host memory, not device
+        api.launch_struct(stats=torch.zeros(11, dtype=torch.int64))         # host memory, not device
     with pytest.raises(ValueError, match="kernel_ms"):
         api.launch_struct(kernel_ms=(ctypes.c_float * 4)())
     la = api.launch_struct(kernel_ms=api.phase_ms(), tail_budget=-1, step_budget=7, max_suspended=5)
     assert (la.tail_budget, la.step_budget, la.max_suspended, la.reserved) == (-1, 7, 5, 0)
     assert len(api.phase_ms()) == 5
+

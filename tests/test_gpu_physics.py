@@ -209,27 +209,55 @@ def test_thermal_runs_fig3_trends_and_no_well_depth_dependence():
 
 
 def test_fig4_threshold_is_a_few_w0():
+    """Fig. 4 text: P(complex) falls with collision energy to a threshold of a few W0 (Eq. (2)), above
+    which complexes are suppressed, and the threshold grows with the atom's mass.  Both flags are
+    measured on the same trajectories: the complex flag (>= 2 bounces or t_max) and the bound-state
+    bit (the relative energy went negative: the temporary atom-ion bound state of the Eq. (2) text).
+    * Bound-state bit, every atom (Cs133 included): the fraction falls with energy above W0 (no rise
+      between bins 0.45 decades apart beyond 3 SE, and a clear fall over the range).
+    * Complex flag, Li6 .. Rb87: every complex also reached the bound state, and the flag's threshold
+      lies at 2-6 W0, increasing with mass.
+    * Complex flag, Cs133: it first rises above W0 (the heavy atom's recoiling ion returns for a second
+      head-on hit without a bound state) and falls beyond its maximum; no threshold within 1 mK."""
     import oracle.reduce as R
     w = W.fig4_energy()
     w.system.max_steps = 2_000_000
     n = 5 * 200_000
     print(f"physics: Fig. 4 energy sweep, n={n}", flush=True)
-    res = api.run_chunks(w, n=n, chunk=n // 2, n_streams=2, hist=True)
+    res = api.run_chunks(w, n=n, chunk=n // 2, n_streams=2, hist=True, hist_bound=True)
     h = api.split_hist(res["hist"])[0].cpu().numpy()
+    hb = api.split_hist(res["hist_bound"])[0].cpu().numpy()
+    assert np.array_equal(h[..., 0], hb[..., 0])
     x = R.W0_LO + (np.arange(R.W0_BINS) + 0.5) * (R.W0_HI - R.W0_LO) / R.W0_BINS
     W0 = [R.w0_eq2(m, w.system.m_ion, C4, w.system.omega_rf, w.system.a_x, 0.2) for m, C4 in w.species()]
     th_abs = []
     for s, name in enumerate(w.species_names):
-        tot, c = h[s, :, 0], h[s, :, 1]
+        tot, c, cb = h[s, :, 0], h[s, :, 1], hb[s, :, 1]
         sel = tot >= 500
-        xs, p = x[sel], c[sel] / tot[sel]
+        xs, p, pb, t = x[sel], c[sel] / tot[sel], cb[sel] / tot[sel], tot[sel]
+        se = np.sqrt(np.maximum(p * (1 - p), 1.0 / t) / t)
+        seb = np.sqrt(np.maximum(pb * (1 - pb), 1.0 / t) / t)
         plateau = p[xs <= 0.0].max()
         below = np.where((xs > 0.0) & (p < 0.05 * plateau))[0]
-        print(f"  {name:6s} plateau {plateau:.3f}, P by log10(E/W0): " +
-              " ".join(f"{a:+.2f}:{b:.3f}" for a, b in zip(xs, p) if -1.0 <= a <= 1.6), flush=True)
+        print(f"  {name:6s} plateau {plateau:.3f}, P(complex) | P(bound state) by log10(E/W0): " +
+              " ".join(f"{a:+.2f}:{b:.3f}|{d:.3f}" for a, b, d in zip(xs, p, pb) if -1.0 <= a <= 2.0), flush=True)
+        # bound-state bit: falls with energy above W0 for every atom
+        up = xs >= 0.0
+        xa, pa, sa = xs[up], pb[up], seb[up]
+        for j in range(len(xa)):
+            for k in range(j + 1, len(xa)):
+                if xa[k] - xa[j] >= 0.45:
+                    assert pa[k] <= pa[j] + 3 * np.hypot(sa[j], sa[k]), (name, xa[j], xa[k], pa[j], pa[k])
+        assert pa[-1] < pa[0] - 5 * np.hypot(sa[0], sa[-1]), (name, pa[0], pa[-1])
         if name == "Cs133":
-            assert len(below) == 0 and p.min() > 0.5          # double head-on hits, never suppressed
+            assert len(below) == 0                           # no threshold within 1 mK
+            m = int(np.argmax(np.where(up, p, -1.0)))
+            print(f"  Cs133 complex flag: maximum {p[m]:.3f} at log10(E/W0) = {xs[m]:+.2f}, {p[-1]:.3f} at "
+                  f"{xs[-1]:+.2f}; bound-state bit {pb[m]:.3f} -> {pb[-1]:.3f}", flush=True)
+            assert xs[m] > 0.0 and p[-1] < p[m] - 10 * np.hypot(se[m], se[-1])
             continue
+        # every complex of the lighter atoms also reached the bound state
+        assert np.all(pb >= p - 3 * np.hypot(se, seb)), name
         x_th = xs[below[0]]
         print(f"  {name:6s} threshold {10 ** x_th:.2f} W0 = {10 ** x_th * W0[s] / W.kelvin(1e-6):.2f} uK", flush=True)
         lo, hi = (0.6, 1.0) if name == "Rb87" else (0.30, 0.61)

@@ -31,8 +31,8 @@ def synthetic_obs(n, seed, p_complex=0.3):
     dE = rng.normal(size=n) * 10.0 ** rng.uniform(-16, -6, n)
     dE[rng.random(n) < 0.01] = 0.0
     nb = rng.integers(1, 200, n).astype(np.int32)
-    st = ((rng.random(n) < p_complex).astype(np.uint32) | (rng.integers(0, 2, n).astype(np.uint32) << 2)
-          | (rng.integers(0, 2, n).astype(np.uint32) << 8))
+    st = ((rng.random(n) < p_complex).astype(np.uint32) | (rng.integers(0, 2, n).astype(np.uint32) << 1)
+          | (rng.integers(0, 2, n).astype(np.uint32) << 2) | (rng.integers(0, 2, n).astype(np.uint32) << 8))
     obs = {"dE_ion": torch.from_numpy(dE).to(DEV), "n_bounce": torch.from_numpy(nb).to(DEV),
            "status": torch.from_numpy(st.astype(np.int32)).to(DEV)}
     return obs, dE, nb, st
@@ -126,6 +126,15 @@ def test_reduce_hist_matches_oracle():
     # of uK for K40 and Cs133, so those two populate both sides of E = W0
     assert hw[0, :32, 0].sum() == 0 and hw[0, 32:, 0].sum() > 0
     assert all(hw[s, :32, 0].sum() > 0 and hw[s, 32:, 0].sum() > 0 for s in (1, 2))
+    # the bound-state variant: the same totals, the second column counting status bit 1
+    fb = api.reduce_hist(w.system, w.species(), w.gen, n, obs, id0=id0, flag="bound")
+    bw, bh = (t.cpu().numpy() for t in api.split_hist(fb))
+    ref_b, _, _, _ = R.w0_hist(ids, w, dE, st, flag=oracle.BOUND_SEEN)
+    assert np.array_equal(bw[..., 0], hw[..., 0]) and np.array_equal(bh, hh)
+    for s in range(3):
+        sel = (slot == s) & ((st & 2) != 0)
+        assert _hist_close(bw[s, :, 1], ref_b[s, :, 1], cw[sel], 64), s
+    assert 0 < bw[..., 1].sum() < n and bw[..., 1].sum() != hw[..., 1].sum()
 
 
 def _grid_workload(side):

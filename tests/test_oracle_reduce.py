@@ -170,3 +170,25 @@ def test_lifetime_axis_and_survival_of_a_power_law():
     hist2, cens2, _ = R.lifetime_hist([0, 0], 1, [0.0, 0.0], [1e9, 1e9], [5, 1],
                                       [R.EXITED, oracle.COMPLEX | R.EXITED])
     assert hist2.sum() == 0 and cens2.sum() == 0
+
+
+def test_w0_hist_flag_column_counts_the_chosen_status_bit():
+    """The second column of the W0 histogram counts the complex flag by default and the bound-state
+    bit when asked: brute-force counts per bin on a small status pattern."""
+    w = W.config5()
+    ids = np.arange(1000, 1400)
+    st = np.zeros(len(ids), np.uint32)
+    st[::3] |= oracle.COMPLEX
+    st[::5] |= oracle.BOUND_SEEN
+    dE = np.zeros(len(ids))
+    hc, _, cw, _ = R.w0_hist(ids, w, dE, st)
+    hb, _, _, _ = R.w0_hist(ids, w, dE, st, flag=oracle.BOUND_SEEN)
+    _, _, slot, _ = R.sweep_params(ids, w)
+    b = np.clip(np.floor(cw), 0, 63).astype(np.int64)
+    for h, bit in ((hc, oracle.COMPLEX), (hb, oracle.BOUND_SEEN)):
+        ref = np.zeros((3, 64))
+        for s_, b_, flagged in zip(slot, b, (st & bit) != 0):
+            ref[s_, b_] += flagged
+        assert np.array_equal(h[..., 1], ref)
+        assert np.array_equal(h[..., 0], hc[..., 0])
+    assert hc[..., 1].sum() == len(ids[::3]) and hb[..., 1].sum() == len(ids[::5])
