@@ -203,6 +203,26 @@ int iat_integrate(const iat_system* sys, const iat_species* species /* host */, 
                   const iat_batch* batch, const iat_obs* obs, const iat_launch* launch,
                   void* ckpt_ws, size_t ckpt_bytes, void* stream);
 
+/* Allocation-free variant of iat_integrate, for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments,
+ * kernels and results as iat_integrate (the same bits per trajectory), except:
+ *  - the call's workspace (queue counters, work buffer, continuation records) is a fixed array
+ *    inside the library, about 21 MiB per GPU, held from the library's first use on that GPU
+ *    until the process ends; the call allocates and frees nothing;
+ *  - n <= IAT_NOALLOC_MAX_N (larger: IAT_EINVAL, nothing enqueued); at most 32768 trajectories per
+ *    call are suspended to the four-lane tail and 4096 of those to the solo level, the others
+ *    finish in the kernel that runs them (same bits);
+ *  - launch.kernel_ms must be NULL (phase timing creates events and waits);
+ *  - every call on one GPU uses that GPU's one array, which keeps the last call's contents (each
+ *    call clears the counters it uses with a fill kernel): calls that can overlap in time on one
+ *    GPU (different streams, or different threads) race and must not be issued; calls ordered in
+ *    one stream are safe;
+ *  - the first call on a device resolves the array's device address (hipGetSymbolAddress): make it
+ *    outside stream capture. */
+#define IAT_NOALLOC_MAX_N 65536
+int iat_integrate_noalloc(const iat_system* sys, const iat_species* species /* host */, int n_species,
+                          const iat_batch* batch, const iat_obs* obs, const iat_launch* launch, void* stream);
+
 /* Reductions of a batch's outputs (the ensemble quantities of Figs. 3 and 4, and the fractal
  * structure of Fig. 1).  obs needs dE_ion, n_bounce and status.  out is device memory; CELLS, both W0 histograms and
  * the LIFETIME counts ADD to it (zero it first to start), so chunks of one sweep accumulate;

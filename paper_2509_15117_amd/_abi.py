@@ -12,13 +12,14 @@ ST_COMPLEX, ST_BOUND_SEEN, ST_EXITED = 1 << 0, 1 << 1, 1 << 2
 ST_TMAX, ST_H_UNDERFLOW, ST_NONFINITE, ST_MAX_STEPS = 1 << 8, 1 << 9, 1 << 10, 1 << 11
 ST_R_UNDERFLOW, ST_WARN_R0, ST_ADJ_SKIPPED = 1 << 12, 1 << 13, 1 << 14
 MAX_SPECIES = 8
+NOALLOC_MAX_N = 65536
 N_STATS, N_PHASES = 11, 5
 GEN_ARRAYS, GEN_GRID, GEN_SWEEP, GEN_THERMAL = 0, 1, 2, 3
 KERNEL_PLAIN, KERNEL_PERSISTENT = 1, 2
 REDUCE_CELLS, REDUCE_W0_HIST, REDUCE_BOXCOUNT, REDUCE_LIFETIME, REDUCE_W0_HIST_BOUND = 1, 2, 3, 4, 5
 W0_BINS, HEAT_BINS, LIFE_BINS, LIFE_SLOT = 64, 256, 96, 98
 
-EXPORTS = ["iat_integrate", "iat_integrate_tangent", "iat_adjoint", "iat_reduce", "iat_adjoint_workspace_bytes",
+EXPORTS = ["iat_integrate", "iat_integrate_noalloc", "iat_integrate_tangent", "iat_adjoint", "iat_reduce", "iat_adjoint_workspace_bytes",
            "iat_fp64_peak", "iat_last_error", "iat_version", "iat_release"]
 
 _d = ctypes.c_double
@@ -84,6 +85,8 @@ def load():
     L.iat_integrate.argtypes = [_P(System), _P(Species), ctypes.c_int, _P(Batch), _P(Obs), _P(Launch), _vp,
                                 ctypes.c_size_t, _vp]
     L.iat_integrate.restype = ctypes.c_int
+    L.iat_integrate_noalloc.argtypes = [_P(System), _P(Species), ctypes.c_int, _P(Batch), _P(Obs), _P(Launch), _vp]
+    L.iat_integrate_noalloc.restype = ctypes.c_int
     L.iat_reduce.argtypes = [_P(System), _P(Species), ctypes.c_int, _P(Batch), _P(Obs), ctypes.c_int, _vp, _vp]
     L.iat_reduce.restype = ctypes.c_int
     L.iat_integrate_tangent.argtypes = [_P(System), _P(Species), ctypes.c_int, _P(Batch), _P(Obs), _vp, _vp,

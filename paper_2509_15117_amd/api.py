@@ -150,14 +150,17 @@ def longest_of(stats) -> tuple:
 
 def integrate(system, species, gen, n: int, *, arrays=None, y0=None, id0=None, kernel="persistent", block=0,
               blocks_per_cu=0, refill_every=0, step_budget=0, y_final=False, counters=True, stats=None, out=None,
-              stream=None, device=None, kernel_ms=None, max_suspended=0, tail_budget=0) -> Dict[str, torch.Tensor]:
+              stream=None, device=None, kernel_ms=None, max_suspended=0, tail_budget=0,
+              noalloc=False) -> Dict[str, torch.Tensor]:
     """Integrate n trajectories on the current GPU; returns device tensors of the observables.
 
     system / gen: objects with the fields of workloads.System / workloads.Generator.
     species: [(m_atom, C4)] in atomic units.  stats: optional uint64[11] device counters (new_stats();
     entry 10 packs the call's longest trajectory, see longest_of()).
     kernel_ms: optional phase_ms() buffer receiving the phase durations (setup, main, tail, solo,
-    observables) measured with HIP events on the stream; the call then waits for completion."""
+    observables) measured with HIP events on the stream; the call then waits for completion.
+    noalloc=True calls iat_integrate_noalloc (the library's fixed workspace; n <= NOALLOC_MAX_N, no
+    kernel_ms; pass `out` to keep the call itself free of allocations)."""
     L = _abi.load()
     device = device or torch.device("cuda", torch.cuda.current_device())
     if out is None:
@@ -168,8 +171,12 @@ def integrate(system, species, gen, n: int, *, arrays=None, y0=None, id0=None, k
     o = obs_struct(out)
     la = launch_struct(kernel, block, blocks_per_cu, refill_every, step_budget, stats, kernel_ms, max_suspended,
                        tail_budget)
-    rc = L.iat_integrate(ctypes.byref(sysv), sp, len(species), ctypes.byref(b), ctypes.byref(o), ctypes.byref(la),
-                         None, 0, _stream_handle(stream))
+    if noalloc:
+        rc = L.iat_integrate_noalloc(ctypes.byref(sysv), sp, len(species), ctypes.byref(b), ctypes.byref(o),
+                                     ctypes.byref(la), _stream_handle(stream))
+    else:
+        rc = L.iat_integrate(ctypes.byref(sysv), sp, len(species), ctypes.byref(b), ctypes.byref(o),
+                             ctypes.byref(la), None, 0, _stream_handle(stream))
     _abi.check(rc)
     return out
 

@@ -300,9 +300,37 @@ void launch_observe(const KParams& P, const Work& W, hipStream_t st)
 }
 }  // namespace iat
 
-extern "C" int iat_integrate(const iat_system* sys, const iat_species* species, int n_species,
+namespace iat {
+
+// One call's device workspace: queue counters | work buffer (n trajectories) | continuation records
+// of the four-lane tail (cap) | continuation records of the solo level (cap2).
+constexpr size_t kRecBytes = 26 * sizeof(double) + 8 * sizeof(int32_t) + sizeof(int64_t);
+constexpr size_t kWorkBytesPerTraj = kWorkDoubles * sizeof(double) + kWorkInts * sizeof(int32_t);
+constexpr size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t workspace_bytes(int64_t n, int64_t cap, int64_t cap2)
+{
+    return 256 + round256((size_t)n * kWorkBytesPerTraj) + (size_t)(cap + cap2) * kRecBytes;
+}
+
+// Largest batch of the allocation-free entry point, and its continuation-record limits (a trajectory
+// that finds no free record keeps running where it is, with the same bits).
+constexpr int64_t kNoAllocMaxN = 1 << 16;
+constexpr int64_t kNoAllocMaxSuspended = 1 << 15;
+constexpr int64_t kNoAllocMaxSolo = 1 << 12;
+constexpr size_t kScratchBytes = workspace_bytes(kNoAllocMaxN, kNoAllocMaxSuspended, kNoAllocMaxSolo);
+
+// Validated arguments of an integration call and the launch shape they resolve to.
+struct IntegrateCall {
+    KParams P;
+    iat_launch L;
+    int64_t n = 0, cap = 0, cap2 = 0;
+    int budget2 = 0;
+    bool ce = false;
+};
+
+static int integrate_prepare(const iat_system* sys, const iat_species* species, int n_species,
                              const iat_batch* batch, const iat_obs* obs, const iat_launch* launch,
-                             void* ckpt_ws, size_t ckpt_bytes, void* stream)
+                             int64_t suspended_limit, int64_t solo_limit, IntegrateCall& c)
 {
     int rc = validate_common(sys, species, n_species, batch);
     if (rc) return rc;
@@ -310,43 +338,42 @@ extern "C" int iat_integrate(const iat_system* sys, const iat_species* species, 
     if (batch->n > 0 &&
         (!obs->angle || !obs->q_transfer || !obs->dE_ion || !obs->t_dwell || !obs->n_bounce || !obs->status))
         return set_error(IAT_EINVAL, "obs: angle, q_transfer, dE_ion, t_dwell, n_bounce and status are required");
-    if (ckpt_ws || ckpt_bytes)
-        return set_error(IAT_ENOTSUP, "checkpointing is done by iat_adjoint itself; pass NULL/0");
-    iat_launch L;
-    rc = resolve_launch(launch, &L);
+    rc = resolve_launch(launch, &c.L);
     if (rc) return rc;
-    if (batch->n == 0) return 0;
-    KParams P;
-    fill_params(P, sys, species, n_species, batch);
-    fill_outputs(P, obs);
-    P.stats = L.stats;
-    P.refill_every = L.refill_every;
-    hipStream_t st = (hipStream_t)stream;
-    int n_cu = 0;
-    rc = device_state(&n_cu);
-    if (rc) return rc;
-    const int64_t n = batch->n;
-    if (n > (int64_t)0x7fffffff * 256) return set_error(IAT_EINVAL, "batch too large for one launch");
-    const unsigned nblk = (unsigned)((n + 255) / 256);
-    P.budget = 0;
-    int64_t cap = 0;
-    if (L.kernel == IAT_KERNEL_PERSISTENT) {
-        P.budget = L.step_budget > 0 ? L.step_budget : (L.step_budget == 0 ? kDefaultBudget : 0);
-        const int64_t lim = L.max_suspended > 0 ? std::min<int64_t>(L.max_suspended, kMaxSuspended) : kMaxSuspended;
-        cap = P.budget > 0 ? std::min<int64_t>(n, lim) : 0;
+    c.n = batch->n;
+    if (c.n > (int64_t)0x7fffffff * 256) return set_error(IAT_EINVAL, "batch too large for one launch");
+    fill_params(c.P, sys, species, n_species, batch);
+    fill_outputs(c.P, obs);
+    c.P.stats = c.L.stats;
+    c.P.refill_every = c.L.refill_every;
+    c.P.budget = 0;
+    c.cap = 0;
+    if (c.L.kernel == IAT_KERNEL_PERSISTENT) {
+        c.P.budget = c.L.step_budget > 0 ? c.L.step_budget : (c.L.step_budget == 0 ? kDefaultBudget : 0);
+        const int64_t lim = c.L.max_suspended > 0 ? std::min<int64_t>(c.L.max_suspended, suspended_limit)
+                                                  : suspended_limit;
+        c.cap = c.P.budget > 0 ? std::min<int64_t>(c.n, lim) : 0;
     }
     // second level: trajectories still running after budget2 steps in the four-lane tail finish
     // one per wave in k_integrate_solo
-    int budget2 = L.tail_budget > 0 ? L.tail_budget : (L.tail_budget == 0 ? (int)kDefaultTailBudget : 0);
-    const int64_t cap2 = (cap > 0 && budget2 > 0) ? std::min<int64_t>(cap, kMaxSolo) : 0;
-    if (cap2 == 0) budget2 = 0;
-    // one stream-ordered block: queue counters | work buffer | continuation records
-    const size_t rec = 26 * sizeof(double) + 8 * sizeof(int32_t) + sizeof(int64_t);
-    const size_t work_bytes = (size_t)n * (kWorkDoubles * sizeof(double) + kWorkInts * sizeof(int32_t));
-    const size_t bytes = 256 + ((work_bytes + 255) / 256) * 256 + (size_t)(cap + cap2) * rec;
-    void* ws = nullptr;
-    if (hipMallocAsync(&ws, bytes, st) != hipSuccess) return set_error(IAT_EHIP, "hipMallocAsync of %zu bytes failed", bytes);
+    c.budget2 = c.L.tail_budget > 0 ? c.L.tail_budget : (c.L.tail_budget == 0 ? (int)kDefaultTailBudget : 0);
+    c.cap2 = (c.cap > 0 && c.budget2 > 0) ? std::min<int64_t>(c.cap, solo_limit) : 0;
+    if (c.cap2 == 0) c.budget2 = 0;
+    // thermal runs leave through the start sphere about the trap centre (CE kernels)
+    c.ce = batch->gen.kind == IAT_GEN_THERMAL;
+    return 0;
+}
+
+// Enqueues the whole call on `st` over the workspace `ws` of workspace_bytes(n, cap, cap2) bytes.
+// Returns the first launch error (0 if none); the caller reports it.
+static hipError_t integrate_enqueue(IntegrateCall& c, void* ws, int n_cu, hipStream_t st, PhaseTimer& timer)
+{
+    KParams& P = c.P;
+    const iat_launch& L = c.L;
+    const int64_t n = c.n, cap = c.cap, cap2 = c.cap2;
+    const unsigned nblk = (unsigned)((n + 255) / 256);
     unsigned long long* q = (unsigned long long*)ws;
+    const size_t work_bytes = (size_t)n * kWorkBytesPerTraj;
     Work W;
     W.n = n;
     W.D = (double*)((char*)ws + 256);
@@ -355,7 +382,7 @@ extern "C" int iat_integrate(const iat_system* sys, const iat_species* species, 
     C.count = q + 1;
     C.head = q + 2;
     C.cap = cap;
-    C.d = (double*)((char*)ws + 256 + ((work_bytes + 255) / 256) * 256);
+    C.d = (double*)((char*)ws + 256 + round256(work_bytes));
     C.n = (int32_t*)(C.d + 26 * cap);
     C.id = (int64_t*)(C.n + 8 * cap);
     Cont C2;
@@ -365,14 +392,13 @@ extern "C" int iat_integrate(const iat_system* sys, const iat_species* species, 
     C2.d = (double*)(C.id + cap);
     C2.n = (int32_t*)(C2.d + 26 * cap2);
     C2.id = (int64_t*)(C2.n + 8 * cap2);
-    PhaseTimer timer(L.kernel_ms, st);
+    // the counters start at zero (a fill kernel, not a memset node, so that the call can be captured)
     hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, st, q, 5);
     timer.mark(0);
     hipLaunchKernelGGL(k_setup, dim3(nblk), dim3(256), 0, st, P, W);
     timer.mark(1);
-    // thermal runs leave through the start sphere about the trap centre (CE kernels)
-    const bool ce = batch->gen.kind == IAT_GEN_THERMAL;
     hipError_t launch_err = hipSuccess;
+    const bool ce = c.ce;
     const void* k_plain = ce ? (const void*)k_integrate_plain<true> : (const void*)k_integrate_plain<false>;
     const void* k_pers = ce ? (const void*)k_integrate_persistent<true> : (const void*)k_integrate_persistent<false>;
     const void* k_tail = ce ? (const void*)k_integrate_tail<true> : (const void*)k_integrate_tail<false>;
@@ -380,6 +406,8 @@ extern "C" int iat_integrate(const iat_system* sys, const iat_species* species, 
     if (L.kernel == IAT_KERNEL_PLAIN) {
         void* args[] = {&P, &W};
         launch_err = hipLaunchKernel(k_plain, dim3((unsigned)((n + L.block - 1) / L.block)), dim3(L.block), args, 0, st);
+        timer.mark(2);
+        timer.mark(3);
     } else {
         int per_cu = L.blocks_per_cu;
         if (per_cu == 0) {
@@ -399,7 +427,7 @@ extern "C" int iat_integrate(const iat_system* sys, const iat_species* species, 
             int64_t blocks4 = (int64_t)n_cu * per_cu4;
             const int64_t need4 = (4 * cap + 255) / 256;
             if (blocks4 > need4) blocks4 = need4;
-            void* args4[] = {&P, &W, &C, &C2, &budget2};
+            void* args4[] = {&P, &W, &C, &C2, &c.budget2};
             const hipError_t e4 = hipLaunchKernel(k_tail, dim3((unsigned)blocks4), dim3(256), args4, 0, st);
             if (launch_err == hipSuccess) launch_err = e4;
         }
@@ -413,18 +441,90 @@ extern "C" int iat_integrate(const iat_system* sys, const iat_species* species, 
             if (launch_err == hipSuccess) launch_err = e1;
         }
     }
-    if (L.kernel == IAT_KERNEL_PLAIN) {
-        timer.mark(2);
-        timer.mark(3);
-    }
     timer.mark(4);
     hipLaunchKernelGGL(k_observe, dim3(nblk), dim3(256), 0, st, P, W);
     timer.mark(5);
+    return launch_err;
+}
+
+// The allocation-free entry point's workspace: one array per device, resolved to a device address
+// once per device with hipGetSymbolAddress (the array's name is not a device address in host code).
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static int scratch_address(void** out)
+{
+    constexpr int kMaxDev = 64;
+    static void* addr[kMaxDev] = {};
+    static std::mutex mu;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev)
+        return set_error(IAT_EHIP, "hipGetDevice failed");
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(IAT_EHIP, "hipGetSymbolAddress of the scratch array failed: %s", hipGetErrorString(e));
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return 0;
+}
+
+}  // namespace iat
+
+extern "C" int iat_integrate(const iat_system* sys, const iat_species* species, int n_species,
+                             const iat_batch* batch, const iat_obs* obs, const iat_launch* launch,
+                             void* ckpt_ws, size_t ckpt_bytes, void* stream)
+{
+    if (ckpt_ws || ckpt_bytes)
+        return set_error(IAT_ENOTSUP, "checkpointing is done by iat_adjoint itself; pass NULL/0");
+    IntegrateCall c;
+    int rc = integrate_prepare(sys, species, n_species, batch, obs, launch, kMaxSuspended, kMaxSolo, c);
+    if (rc) return rc;
+    if (c.n == 0) return 0;
+    int n_cu = 0;
+    rc = device_state(&n_cu);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t bytes = workspace_bytes(c.n, c.cap, c.cap2);
+    void* ws = nullptr;
+    if (hipMallocAsync(&ws, bytes, st) != hipSuccess) return set_error(IAT_EHIP, "hipMallocAsync of %zu bytes failed", bytes);
+    PhaseTimer timer(c.L.kernel_ms, st);
+    const hipError_t launch_err = integrate_enqueue(c, ws, n_cu, st, timer);
     if (hipFreeAsync(ws, st) != hipSuccess) return set_error(IAT_EHIP, "hipFreeAsync failed");
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = launch_err;
     if (e != hipSuccess) return set_error(IAT_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
     return timer.finish();
+}
+
+extern "C" int iat_integrate_noalloc(const iat_system* sys, const iat_species* species, int n_species,
+                                     const iat_batch* batch, const iat_obs* obs, const iat_launch* launch,
+                                     void* stream)
+{
+    IntegrateCall c;
+    int rc = integrate_prepare(sys, species, n_species, batch, obs, launch, kNoAllocMaxSuspended, kNoAllocMaxSolo, c);
+    if (rc) return rc;
+    if (c.n > kNoAllocMaxN)
+        return set_error(IAT_EINVAL, "iat_integrate_noalloc: n = %lld is above its limit of %lld trajectories",
+                         (long long)c.n, (long long)kNoAllocMaxN);
+    if (c.L.kernel_ms)
+        return set_error(IAT_EINVAL, "iat_integrate_noalloc: phase timing (launch.kernel_ms) is not available");
+    if (c.n == 0) return 0;
+    int n_cu = 0;
+    rc = device_state(&n_cu);
+    if (rc) return rc;
+    void* ws = nullptr;
+    rc = scratch_address(&ws);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    PhaseTimer timer(nullptr, st);
+    const hipError_t launch_err = integrate_enqueue(c, ws, n_cu, st, timer);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = launch_err;
+    if (e != hipSuccess) return set_error(IAT_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+    return 0;
 }
 
 extern "C" const char* iat_last_error(void) { return iat::last_error(); }

@@ -157,3 +157,32 @@ def test_launch_buffers_are_size_checked_before_the_call():
     assert (la.tail_budget, la.step_budget, la.max_suspended, la.reserved) == (-1, 7, 5, 0)
     assert len(api.phase_ms()) == 5
 
+
+def test_noalloc_refuses_oversized_batches_and_timing_without_gpu():
+    """The allocation-free entry point holds its workspace in a fixed array: a batch above its limit
+    and phase timing (events and a wait) are refused before the GPU is touched."""
+    from paper_2509_15117_amd import api
+    L = _abi.load()
+    w = W.config5()
+    txt = open(os.path.join(ROOT, "include", "iat.h")).read()
+    assert f"#define IAT_NOALLOC_MAX_N {_abi.NOALLOC_MAX_N}" in txt
+    sysv = api.system_struct(w.system)
+    sp = api.species_array(w.species())
+
+    def call(n, launch):
+        b = api.batch_struct(n, w.gen)
+        rc = L.iat_integrate_noalloc(ctypes.byref(sysv), sp, 3, ctypes.byref(b), ctypes.byref(_obs_dummy()),
+                                     ctypes.byref(launch), None)
+        return rc, L.iat_last_error().decode()
+
+    rc, msg = call(_abi.NOALLOC_MAX_N + 1, _abi.Launch())
+    assert rc == _abi.IAT_EINVAL and "limit" in msg and str(_abi.NOALLOC_MAX_N) in msg, msg
+    rc, msg = call(1 << 40, _abi.Launch())
+    assert rc == _abi.IAT_EINVAL, msg
+    rc, msg = call(4, api.launch_struct(kernel_ms=api.phase_ms()))
+    assert rc == _abi.IAT_EINVAL and "kernel_ms" in msg, msg
+    rc, msg = call(0, _abi.Launch())
+    assert rc == 0, msg                              # nothing to do: no GPU call
+    la = api.launch_struct(block=100)
+    rc, msg = call(4, la)
+    assert rc == _abi.IAT_EINVAL and "block" in msg, msg
