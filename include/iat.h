@@ -158,9 +158,9 @@ enum { IAT_KERNEL_PLAIN = 1, IAT_KERNEL_PERSISTENT = 2 };
 
 /* Launch shape.  kernel: PLAIN = one lane per trajectory, one launch per batch;
  * PERSISTENT = resident grid whose lanes refill from a device work queue; trajectories that
- * outlive step_budget continue four lanes per trajectory in a second kernel, and those that
- * outlive tail_budget there finish in a third, one trajectory per wave.  All kernels give the
- * same bits for the same trajectory.
+ * outlive step_budget continue four lanes per trajectory in a second kernel, and the last ones
+ * running there finish in a third, one trajectory per wave (see tail_budget).  All kernels give
+ * the same bits for the same trajectory.
  * Zero fields take defaults.  stats, if not NULL, is a device uint64[11] to which the
  * call ADDS: [0] RHS evaluations, [1] accepted steps, [2] rejected steps,
  * [3] trajectories finished, [4] issued step slots (one-lane kernels: wave iterations x 64;
@@ -187,10 +187,13 @@ typedef struct {
                                  one call (continuation records of 248 B each, allocated
                                  with the call's workspace); the others finish in the
                                  one-lane kernel.  0 = min(n, 2^23)                      */
-    int32_t tail_budget;      /* PERSISTENT: attempted steps in the four-lane tail after which
-                                 a trajectory is suspended again and finished alone in its
-                                 wave (at most min(max_suspended, 2^16) of them per call; the
-                                 others stay in the tail); 0 = default (50000), -1 = never */
+    int32_t tail_budget;      /* PERSISTENT: when a trajectory in the four-lane tail is
+                                 suspended again and finished alone in its wave (at most
+                                 min(max_suspended, 2^16) of them per call; the others stay
+                                 in the tail).  0 = default: once at most 4 per compute unit
+                                 (the solo level's waves) of the trajectories that entered the
+                                 tail are still running or waiting there; > 0: after this many
+                                 attempted steps in the tail; -1 = never                  */
     int32_t reserved;         /* must be 0                                                */
     uint64_t* stats;
     float* kernel_ms;

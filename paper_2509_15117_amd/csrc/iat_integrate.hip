@@ -23,7 +23,6 @@ namespace iat {
 
 constexpr int64_t kDefaultBudget = 20000;        // attempted steps before a trajectory moves to 4 lanes
 constexpr int64_t kMaxSuspended = 1 << 23;       // continuation records per call (248 B each)
-constexpr int64_t kDefaultTailBudget = 50000;   // attempted steps in the four-lane tail before the solo level
 constexpr int64_t kMaxSolo = 1 << 16;            // records of the solo level per call
 
 __device__ __forceinline__ uint64_t wave_sum(uint64_t v)
@@ -175,13 +174,16 @@ __global__ void __launch_bounds__(256) k_integrate_persistent(KParams P, Work W,
 
 // Finishes suspended trajectories with four lanes each (one per axis): the per-step latency of
 // a long-lived complex is what bounds a batch's wall time.  QUADS trajectories share a wave.
-// With budget2 > 0, a trajectory that has run budget2 more attempted steps here is suspended
-// again into C2 (while its slots last) and its quad takes new work; k_integrate_solo finishes
-// those one per wave, so the longest complexes run without wave or SIMD neighbours.  Counters:
-// stats[si] RHS evaluations and stats[si + 1] trajectories finished in this kernel.
+// Trajectories move on to k_integrate_solo, which finishes them one per wave so that the longest
+// complexes run without wave or SIMD neighbours, by one of two rules: with budget2 > 0, after
+// budget2 more attempted steps here; with pop_limit > 0, once at most pop_limit of the records this
+// kernel resumes are still running or waiting (`gone` counts the finished and moved ones), i.e. once
+// the solo level's waves can hold them all.  A trajectory is moved (suspended again into C2, while
+// its slots last) after the step it is on, and its quad takes new work.  Counters: stats[si] RHS
+// evaluations and stats[si + 1] trajectories finished in this kernel.
 template <bool CE, int QUADS>
 __device__ __forceinline__ void tail_run(const KParams& P, const Work& W, const Cont& C, const Cont& C2,
-                                         int budget2, int si)
+                                         int budget2, int64_t pop_limit, unsigned long long* gone, int si)
 {
     const int lane = __lane_id();
     const int qlead = lane & ~3;
@@ -196,7 +198,8 @@ __device__ __forceinline__ void tail_run(const KParams& P, const Work& W, const 
     int64_t i = -1;
     int32_t resumed_at = 0, resumed_rhs = 0;
     uint64_t tail_rhs = 0, tail_done = 0;
-    bool active = false, need = (lane >> 2) < QUADS, may_suspend = budget2 > 0 && C2.cap > 0;
+    bool active = false, need = (lane >> 2) < QUADS, may_suspend = (budget2 > 0 || pop_limit > 0) && C2.cap > 0;
+    bool few_left = false;       // pop_limit rule: the remaining population fits the solo level
     const Tab B = tab_in_registers();
     const StepK K = step_k_in_registers(P);
     for (;;) {
@@ -218,6 +221,9 @@ __device__ __forceinline__ void tail_run(const KParams& P, const Work& W, const 
             }
         }
         if (!__any(active)) break;
+        // every lane reads the counter in the same load, so the flag is wave-uniform
+        if (pop_limit > 0 && may_suspend && !few_left && (iters & 63) == 0)
+            few_left = total - (int64_t)__hip_atomic_load(gone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= pop_limit;
         if (active && !T.S.done) traj4_advance_k<CE, QUADS == 1>(P, K, T, B);
         ++iters;
         if (active && T.S.done) {
@@ -230,6 +236,7 @@ __device__ __forceinline__ void tail_run(const KParams& P, const Work& W, const 
                 st.useful += T.S.nacc + T.S.nrej - resumed_at;
                 tail_rhs += (uint64_t)(T.S.nrhs - resumed_rhs);
                 tail_done += 1;
+                if (pop_limit > 0) atomicAdd(gone, 1ull);
                 if (P.stats) {
                     const uint64_t key = longest_key(P, i, T.S.nacc, T.S.nrej);
                     st.longest = key > st.longest ? key : st.longest;
@@ -237,7 +244,8 @@ __device__ __forceinline__ void tail_run(const KParams& P, const Work& W, const 
             }
             active = false;
             need = (lane >> 2) < QUADS;
-        } else if (active && may_suspend && T.S.nacc + T.S.nrej - resumed_at >= budget2) {
+        } else if (active && may_suspend &&
+                   (budget2 > 0 ? T.S.nacc + T.S.nrej - resumed_at >= budget2 : few_left)) {
             // quad-uniform: the whole quad holds the same scalar state
             unsigned long long s2 = 0;
             if (leader) s2 = atomicAdd(C2.count, 1ull);
@@ -247,6 +255,7 @@ __device__ __forceinline__ void tail_run(const KParams& P, const Work& W, const 
                 if (leader) {
                     st.useful += T.S.nacc + T.S.nrej - resumed_at;
                     tail_rhs += (uint64_t)(T.S.nrhs - resumed_rhs);
+                    if (pop_limit > 0) atomicAdd(gone, 1ull);
                 }
                 active = false;
                 need = true;   // a quad that suspends is one of the wave's QUADS quads
@@ -267,16 +276,17 @@ __device__ __forceinline__ void tail_run(const KParams& P, const Work& W, const 
 }
 
 template <bool CE>
-__global__ void __launch_bounds__(256) k_integrate_tail(KParams P, Work W, Cont C, Cont C2, int budget2)
+__global__ void __launch_bounds__(256) k_integrate_tail(KParams P, Work W, Cont C, Cont C2, int budget2,
+                                                        int64_t pop_limit, unsigned long long* gone)
 {
-    tail_run<CE, 16>(P, W, C, C2, budget2, 6);
+    tail_run<CE, 16>(P, W, C, C2, budget2, pop_limit, gone, 6);
 }
 
 // One trajectory (one quad) per wave, launched one wave per block.
 template <bool CE>
 __global__ void __launch_bounds__(64) k_integrate_solo(KParams P, Work W, Cont C)
 {
-    tail_run<CE, 1>(P, W, C, C, 0, 8);
+    tail_run<CE, 1>(P, W, C, C, 0, 0, nullptr, 8);
 }
 
 __global__ void k_reset_counters(unsigned long long* q, int n)
@@ -325,6 +335,7 @@ struct IntegrateCall {
     iat_launch L;
     int64_t n = 0, cap = 0, cap2 = 0;
     int budget2 = 0;
+    bool pop_rule = false;       // move to the solo level once the tail's population fits it
     bool ce = false;
 };
 
@@ -354,11 +365,16 @@ static int integrate_prepare(const iat_system* sys, const iat_species* species, 
                                                   : suspended_limit;
         c.cap = c.P.budget > 0 ? std::min<int64_t>(c.n, lim) : 0;
     }
-    // second level: trajectories still running after budget2 steps in the four-lane tail finish
-    // one per wave in k_integrate_solo
-    c.budget2 = c.L.tail_budget > 0 ? c.L.tail_budget : (c.L.tail_budget == 0 ? (int)kDefaultTailBudget : 0);
-    c.cap2 = (c.cap > 0 && c.budget2 > 0) ? std::min<int64_t>(c.cap, solo_limit) : 0;
-    if (c.cap2 == 0) c.budget2 = 0;
+    // second level: trajectories still running in the four-lane tail finish one per wave in
+    // k_integrate_solo, moved there after tail_budget steps, or (default) once the tail's
+    // remaining population fits the solo level's waves
+    c.budget2 = c.L.tail_budget > 0 ? c.L.tail_budget : 0;
+    c.pop_rule = c.L.tail_budget == 0;
+    c.cap2 = (c.cap > 0 && (c.budget2 > 0 || c.pop_rule)) ? std::min<int64_t>(c.cap, solo_limit) : 0;
+    if (c.cap2 == 0) {
+        c.budget2 = 0;
+        c.pop_rule = false;
+    }
     // thermal runs leave through the start sphere about the trap centre (CE kernels)
     c.ce = batch->gen.kind == IAT_GEN_THERMAL;
     return 0;
@@ -393,7 +409,8 @@ static hipError_t integrate_enqueue(IntegrateCall& c, void* ws, int n_cu, hipStr
     C2.n = (int32_t*)(C2.d + 26 * cap2);
     C2.id = (int64_t*)(C2.n + 8 * cap2);
     // the counters start at zero (a fill kernel, not a memset node, so that the call can be captured)
-    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, st, q, 5);
+    unsigned long long* gone = q + 5;
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, st, q, 6);
     timer.mark(0);
     hipLaunchKernelGGL(k_setup, dim3(nblk), dim3(256), 0, st, P, W);
     timer.mark(1);
@@ -427,7 +444,9 @@ static hipError_t integrate_enqueue(IntegrateCall& c, void* ws, int n_cu, hipStr
             int64_t blocks4 = (int64_t)n_cu * per_cu4;
             const int64_t need4 = (4 * cap + 255) / 256;
             if (blocks4 > need4) blocks4 = need4;
-            void* args4[] = {&P, &W, &C, &C2, &c.budget2};
+            // the solo level's waves: one per SIMD (k_integrate_solo's launch below)
+            int64_t pop_limit = c.pop_rule ? std::min<int64_t>((int64_t)n_cu * 4, cap2) : 0;
+            void* args4[] = {&P, &W, &C, &C2, &c.budget2, &pop_limit, &gone};
             const hipError_t e4 = hipLaunchKernel(k_tail, dim3((unsigned)blocks4), dim3(256), args4, 0, st);
             if (launch_err == hipSuccess) launch_err = e4;
         }
