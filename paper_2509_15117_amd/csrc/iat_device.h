@@ -598,28 +598,41 @@ __device__ __forceinline__ StepK step_k_in_registers(const KParams& P)
     return k;
 }
 
+// A branch condition of the step, as is, or (UNI) as a wave-uniform value for kernels in which every
+// lane of the wave holds the same scalar state: a ballot turns it into a scalar condition, so the
+// branch needs no exec-mask bookkeeping.  The value of the condition is the same either way.
+template <bool UNI>
+__device__ __forceinline__ bool cond(bool c)
+{
+    if constexpr (UNI)
+        return __builtin_amdgcn_ballot_w64(c) != 0;
+    else
+        return c;
+}
+
 // Step prologue shared by both forms: picks h and handles the stops that precede a step.
 // Returns false when the trajectory stopped.
+template <bool UNI = false>
 __device__ __forceinline__ bool step_prologue(const StepK& K, Scal& S, double& h, bool& fin)
 {
     fin = false;
-    if (S.mode != 0) {
+    if (cond<UNI>(S.mode != 0)) {
         const double x0 = S.rho_prev, g0 = S.s_prev, x1 = S.sx1, g1 = S.sg1;
         h = (g1 != g0) ? x1 - g1 * (x1 - x0) / (g1 - g0) : x1;
         h = h < 0.0 ? 0.0 : (h > S.h ? S.h : h);
         return true;
     }
-    if (S.nacc >= K.max_steps) {
+    if (cond<UNI>(S.nacc >= K.max_steps)) {
         S.status |= IAT_ST_MAX_STEPS;
         S.done = 1;
         return false;
     }
     h = S.h;
-    if (h >= K.tau_max - S.tau) {
+    if (cond<UNI>(h >= K.tau_max - S.tau)) {
         h = K.tau_max - S.tau;
         fin = true;
     }
-    if (!fin && h < K.hmin) {
+    if (cond<UNI>(!fin && h < K.hmin)) {
         S.status |= IAT_ST_H_UNDERFLOW;
         S.done = 1;
         return false;
@@ -643,20 +656,20 @@ enum StepOutcome { OUT_SECANT_CONT = 0, OUT_SECANT_DONE, OUT_REJECT, OUT_NONFINI
 // and the relative speed^2 of the new state; e_prev, e_new, se_new: the exit geometry of the step
 // start and of the new state when CE (else the separation is the exit geometry); fin: final step.
 // In secant mode only the exit radius of the new state is used.
-template <bool CE = false>
+template <bool CE = false, bool UNI = false>
 __device__ __forceinline__ StepOutcome step_epilogue(const StepK& K, Scal& S, const Lane& L, double h, bool fin,
                                                      double en, bool finite, double rho_new, double s_new,
                                                      double w2, double e_prev = 0.0, double e_new = 0.0,
                                                      double se_new = 0.0)
 {
-    if (S.mode != 0) {
+    if (cond<UNI>(S.mode != 0)) {
         S.nrhs += 5;
         const double g2 = sqrt(CE ? e_new : rho_new) - K.r0;
         S.rho_prev = S.sx1;
         S.s_prev = S.sg1;
         S.sx1 = h;
         S.sg1 = g2;
-        if (++S.mode > 4) {
+        if (cond<UNI>(++S.mode > 4)) {
             S.tau = S.tau + h;
             S.status |= IAT_ST_EXITED;
             S.done = 1;
@@ -665,34 +678,34 @@ __device__ __forceinline__ StepOutcome step_epilogue(const StepK& K, Scal& S, co
         return OUT_SECANT_CONT;
     }
     S.nrhs += 6;
-    if (!(en <= 1.0)) {
+    if (cond<UNI>(!(en <= 1.0))) {
         S.nrej++;
         S.h = h * reject_factor(en);
         S.last_rej = 1;
         return OUT_REJECT;
     }
     S.nacc++;
-    if (!finite) {
+    if (cond<UNI>(!finite)) {
         S.status |= IAT_ST_NONFINITE;
         S.done = 1;
         return OUT_NONFINITE;
     }
     const double tau_new = fin ? K.tau_max : S.tau + h;
     // bounce: periapsis of the relative motion inside r_b
-    if (S.s_prev < 0.0 && s_new >= 0.0 && fmin(S.rho_prev, rho_new) < L.rm2 * K.rb_ratio2) {
+    if (cond<UNI>(S.s_prev < 0.0 && s_new >= 0.0 && fmin(S.rho_prev, rho_new) < L.rm2 * K.rb_ratio2)) {
         if (S.nb == 0) S.tau_first = tau_new;
         S.tau_last = tau_new;
         S.nb++;
     }
-    if (bound_state(L, rho_new, w2)) S.status |= IAT_ST_BOUND_SEEN;
-    if (rho_new < 0.01 * L.rm2) {   // separation below 0.1 r_m: integration broken
+    if (cond<UNI>(bound_state(L, rho_new, w2))) S.status |= IAT_ST_BOUND_SEEN;
+    if (cond<UNI>(rho_new < 0.01 * L.rm2)) {   // separation below 0.1 r_m: integration broken
         S.tau = tau_new;
         S.status |= IAT_ST_R_UNDERFLOW;
         S.done = 1;
         return OUT_STOP_RFLOOR;
     }
     const double ex_prev = CE ? e_prev : S.rho_prev, ex_new = CE ? e_new : rho_new;
-    if (ex_prev <= K.r0sq && ex_new > K.r0sq && (CE ? se_new : s_new) > 0.0) {
+    if (cond<UNI>(ex_prev <= K.r0sq && ex_new > K.r0sq && (CE ? se_new : s_new) > 0.0)) {
         // keep y_n; the next four steps are secant iterates, (x0, g0) kept in (rho_prev, s_prev)
         S.mode = 1;
         S.s_prev = sqrt(ex_prev) - K.r0;
@@ -705,7 +718,7 @@ __device__ __forceinline__ StepOutcome step_epilogue(const StepK& K, Scal& S, co
     S.tau = tau_new;
     S.rho_prev = rho_new;
     S.s_prev = s_new;
-    if (fin) {
+    if (cond<UNI>(fin)) {
         S.status |= IAT_ST_TMAX;
         S.done = 1;
         S.h = h;
@@ -1310,6 +1323,179 @@ __device__ __forceinline__ void traj4_store(const Work& W, int64_t i, const Traj
         W.d(9 + lane_in_quad, i) = T.vi;
     }
     if (lane_in_quad == 0) work_store_scal(W, i, T.S);
+}
+
+// ---------------------------------------------------------------------------------------
+// Eight lanes per trajectory, for the solo level (one trajectory per wave).  Lanes 0, 1, 2 of the
+// octet hold the atom's coordinate 0, 1, 2 and lanes 7, 6, 5 the ion's, so that the half-row mirror
+// pairs every lane with the same axis of the other body; lanes 3 and 4 shadow axis 2.  The ion lanes
+// keep their position, velocity and accelerations negated: the separation d_k = X_atom,k - X_ion,k is
+// then the sum of a lane's value and its partner's in every lane (negation is exact, so the sum rounds
+// as the difference does in the other forms).  Each lane carries one coordinate, so the stage sums,
+// the fifth-order solution and the error estimate take half the instructions of the four-lane form,
+// and the six small-angle series of the stage cosines run in one round; every value is formed by the
+// same expression as in the other forms, so the bits are the same.
+// ---------------------------------------------------------------------------------------
+struct Traj8 {
+    double x, v, F1;   // this lane's coordinate (negated on ion lanes)
+    Scal S;
+    Lane L;
+};
+
+__device__ __forceinline__ int oct_lane() { return (int)(__lane_id() & 7); }
+__device__ __forceinline__ bool oct_atom() { return oct_lane() < 4; }
+__device__ __forceinline__ int oct_axis()
+{
+    const int l = oct_lane();
+    return l < 4 ? min(l, 2) : min(7 - l, 2);
+}
+
+// the other body's same axis: lane 7 - l of the half row (two 32-bit half-row-mirror moves)
+__device__ __forceinline__ double oct_partner(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x141, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x141, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double oct_max(double v) { return quad_max(fmax(v, oct_partner(v))); }
+__device__ __forceinline__ int oct_or(int v)
+{
+    return quad_or(v | __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false));
+}
+
+// Stage cosines for the eight-lane form: the values of stage_cos, with lanes 0..5 each evaluating one
+// of the six small-angle series (lane 0 the phase remainder, lanes 1..5 the offsets c2 h, c3 h, c4 h,
+// c5 h and h) in a single round, gathered with row broadcasts.
+__device__ __forceinline__ StageCos stage_cos8(double tau, double phase0, double h, const Tab& T)
+{
+    const int l = oct_lane();
+    const double cl = l == 1 ? T.c2 : (l == 2 ? T.c3 : (l == 3 ? T.c4 : (l == 4 ? T.c5 : 1.0)));
+    double k;
+    const double r = phase_reduce(tau + phase0, k);
+    asm volatile("" ::"v"(r));
+    const double a = l == 0 ? r : cl * h;
+    double c, s;
+    small_sincos(a, c, s);
+    double sb, cb;
+    phase_quadrant(k, quad_bcast<0, true>(c), quad_bcast<0, true>(s), sb, cb);
+    StageCos C;
+    C.c2 = cos_comb(cb, sb, quad_bcast<1, true>(c), quad_bcast<1, true>(s));
+    C.c3 = cos_comb(cb, sb, quad_bcast<2, true>(c), quad_bcast<2, true>(s));
+    C.c4 = cos_comb(cb, sb, quad_bcast<3, true>(c), quad_bcast<3, true>(s));
+    C.c5 = cos_comb(cb, sb, quad_bcast<4, true>(c), quad_bcast<4, true>(s));
+    C.c6 = cos_comb(cb, sb, quad_bcast<5, true>(c), quad_bcast<5, true>(s));
+    return C;
+}
+
+// Acceleration of this lane's coordinate at stage position X (negated on ion lanes), by the
+// expressions of acc_atom and acc_ion: d_k = X + partner is X_atom,k - X_ion,k in every lane.
+__device__ __forceinline__ double accel8(const KParams& P, const Lane& L, bool atom, double kA, double qr,
+                                         double cs, double X)
+{
+    const double dk = X + oct_partner(X);
+    const double d0 = quad_bcast<0, true>(dk), d1 = quad_bcast<1, true>(dk), d2 = quad_bcast<2, true>(dk);
+    const double s = force_scale(L, d0, d1, d2);
+    const double qc = L.qx_half * cs;
+    const double aa = acc_atom(L, s, dk);
+    const double ai = acc_ion(P.inv_mi, s, dk, kA, qc, qr, -X);
+    return atom ? aa : -ai;
+}
+
+// One attempted step (or secant iterate) of the eight-lane form.
+template <bool CE>
+__device__ __forceinline__ void traj8_advance(const KParams& P, const StepK& K, Traj8& T, const Tab& B, bool atom,
+                                              double kA, double qr)
+{
+    double h;
+    bool fin;
+    if (!step_prologue<true>(K, T.S, h, fin)) return;
+    const bool exiting = T.S.mode != 0;
+    const double hh = h * h;
+    const StageCos C = stage_cos8(T.S.tau, T.L.phase0, h, B);
+    const double F2 = accel8(P, T.L, atom, kA, qr, C.c2, stage2(T.x, T.v, h, B));
+    const double F3 = accel8(P, T.L, atom, kA, qr, C.c3, stage3(T.x, T.v, h, hh, T.F1, B));
+    const double F4 = accel8(P, T.L, atom, kA, qr, C.c4, stage4(T.x, T.v, h, hh, T.F1, F2, B));
+    const double F5 = accel8(P, T.L, atom, kA, qr, C.c5, stage5(T.x, T.v, h, hh, T.F1, F2, F3, B));
+    const double F6 = accel8(P, T.L, atom, kA, qr, C.c6, stage6(T.x, T.v, h, hh, T.F1, F2, F3, F4, B));
+    const double x5 = sol_x(T.x, T.v, h, hh, T.F1, F2, F3, F4, F5, B);
+    const double v5 = sol_v(T.v, h, T.F1, F3, F4, F5, F6, B);
+    double en = 0.0, F7 = 0.0;
+    bool finite = true;
+    if (cond<true>(!exiting)) {
+        F7 = accel8(P, T.L, atom, kA, qr, C.c6, x5);
+        const double rx = err_ratio(err_x(hh, T.F1, F2, F3, F4, F5, F6, B), T.x, x5, K.rtol, K.atol);
+        const double rv = err_ratio(err_v(h, T.F1, F3, F4, F5, F6, F7, B), T.v, v5, K.rtol, K.atol);
+        const int bad = oct_or((ratio_bad(rx) || ratio_bad(rv)) ? 1 : 0);
+        const int nonfin = oct_or((is_finite(x5) && is_finite(v5)) ? 0 : 1);
+        const double m = oct_max(fmax(rx, rv));
+        en = bad ? __builtin_nan("") : m;
+        finite = nonfin == 0;
+    }
+    const double dk = x5 + oct_partner(x5), wk = v5 + oct_partner(v5);
+    const double d0 = quad_bcast<0, true>(dk), d1 = quad_bcast<1, true>(dk), d2 = quad_bcast<2, true>(dk);
+    const double w0 = quad_bcast<0, true>(wk), w1 = quad_bcast<1, true>(wk), w2 = quad_bcast<2, true>(wk);
+    const double rho_new = dot3(d0, d1, d2, d0, d1, d2);
+    const double s_new = dot3(d0, d1, d2, w0, w1, w2);
+    const double ww = dot3(w0, w1, w2, w0, w1, w2);
+    double e_prev = 0.0, e_new = 0.0, se_new = 0.0;
+    if (CE) {
+        const double p0 = quad_bcast<0, true>(T.x), p1 = quad_bcast<1, true>(T.x), p2 = quad_bcast<2, true>(T.x);
+        const double a0 = quad_bcast<0, true>(x5), a1 = quad_bcast<1, true>(x5), a2 = quad_bcast<2, true>(x5);
+        const double u0 = quad_bcast<0, true>(v5), u1 = quad_bcast<1, true>(v5), u2 = quad_bcast<2, true>(v5);
+        e_prev = dot3(p0, p1, p2, p0, p1, p2);
+        e_new = dot3(a0, a1, a2, a0, a1, a2);
+        se_new = dot3(a0, a1, a2, u0, u1, u2);
+    }
+    const StepOutcome o =
+        step_epilogue<CE, true>(K, T.S, T.L, h, fin, en, finite, rho_new, s_new, ww, e_prev, e_new, se_new);
+    const bool moved = o == OUT_SECANT_DONE || o == OUT_STOP_RFLOOR || o == OUT_ACCEPT || o == OUT_TMAX;
+    T.x = moved ? x5 : T.x;
+    T.v = moved ? v5 : T.v;
+    T.F1 = (o == OUT_ACCEPT || o == OUT_TMAX) ? F7 : T.F1;
+}
+
+// A record of the continuation layout (cont_save) into the eight-lane form.
+__device__ inline void cont_load8(const Work& W, const Cont& C, int64_t slot, bool atom, int ax, Traj8& T, int64_t& i)
+{
+    const int64_t c = C.cap;
+    i = C.id[slot];
+    const int comp = atom ? ax : 3 + ax;
+    const double x = C.d[(0 + comp) * c + slot], v = C.d[(6 + comp) * c + slot], f = C.d[(12 + comp) * c + slot];
+    T.x = atom ? x : -x;
+    T.v = atom ? v : -v;
+    T.F1 = atom ? f : -f;
+    Scal& S = T.S;
+    S.tau = C.d[18 * c + slot];
+    S.h = C.d[19 * c + slot];
+    S.rho_prev = C.d[20 * c + slot];
+    S.s_prev = C.d[21 * c + slot];
+    S.sx1 = C.d[22 * c + slot];
+    S.sg1 = C.d[23 * c + slot];
+    S.tau_first = C.d[24 * c + slot];
+    S.tau_last = C.d[25 * c + slot];
+    S.nacc = C.n[0 * c + slot];
+    S.nrej = C.n[1 * c + slot];
+    S.nrhs = C.n[2 * c + slot];
+    S.nb = C.n[3 * c + slot];
+    S.status = (uint32_t)C.n[4 * c + slot];
+    S.mode = (uint32_t)C.n[5 * c + slot];
+    S.last_rej = C.n[6 * c + slot];
+    S.done = 0;
+    work_lane(W, i, T.L);
+}
+
+// Final state into the work buffer: lanes 0..2 the atom's coordinates, lanes 7..5 the ion's (sign
+// restored), lane 0 the scalar state.
+__device__ __forceinline__ void traj8_store(const Work& W, int64_t i, const Traj8& T, int l)
+{
+    if (l < 3) {
+        W.d(l, i) = T.x;
+        W.d(6 + l, i) = T.v;
+    } else if (l >= 5) {
+        W.d(3 + (7 - l), i) = -T.x;
+        W.d(9 + (7 - l), i) = -T.v;
+    }
+    if (l == 0) work_store_scal(W, i, T.S);
 }
 
 }  // namespace iat

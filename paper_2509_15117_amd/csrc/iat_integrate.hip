@@ -282,11 +282,68 @@ __global__ void __launch_bounds__(256) k_integrate_tail(KParams P, Work W, Cont 
     tail_run<CE, 16>(P, W, C, C2, budget2, pop_limit, gone, 6);
 }
 
-// One trajectory (one quad) per wave, launched one wave per block.
-template <bool CE>
-__global__ void __launch_bounds__(64) k_integrate_solo(KParams P, Work W, Cont C)
+// 64-bit value of the wave's first active lane, as a wave-uniform (scalar) value
+__device__ __forceinline__ uint64_t first_lane_u64(uint64_t v)
 {
-    tail_run<CE, 1>(P, W, C, C, 0, 0, nullptr, 8);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// The solo level: one trajectory per wave, eight lanes per trajectory (every octet of the wave runs a
+// copy of it, so the whole wave follows one control path and its branches are uniform), launched in
+// blocks of four waves, one block per compute unit, so that the dispatcher puts one wave on each SIMD.
+// Each wave takes records from C one at a time.  Counters: stats[8] RHS evaluations and stats[9]
+// trajectories finished here.
+template <bool CE>
+__global__ void __launch_bounds__(256) k_integrate_solo(KParams P, Work W, Cont C)
+{
+    const int lane = __lane_id();
+    const int l = lane & 7;
+    const bool atom = l < 4;
+    const int ax = atom ? min(l, 2) : min(7 - l, 2);
+    const double kA = ax == 0 ? P.kA[0] : (ax == 1 ? P.kA[1] : P.kA[2]);
+    const double qr = ax == 0 ? P.q_ratio[0] : (ax == 1 ? P.q_ratio[1] : P.q_ratio[2]);
+    const unsigned long long cnt = *C.count;
+    const int64_t total = (int64_t)(cnt < (unsigned long long)C.cap ? cnt : (unsigned long long)C.cap);
+    const Tab B = tab_in_registers();
+    const StepK K = step_k_in_registers(P);
+    LaneStats st;
+    uint64_t iters = 0, solo_rhs = 0, solo_done = 0;
+    for (;;) {
+        unsigned long long slot = 0;
+        if (lane == 0) slot = atomicAdd(C.head, 1ull);
+        slot = first_lane_u64(slot);
+        if ((int64_t)slot >= total) break;
+        Traj8 T;
+        int64_t i;
+        cont_load8(W, C, (int64_t)slot, atom, ax, T, i);
+        const int32_t resumed_at = T.S.nacc + T.S.nrej, resumed_rhs = T.S.nrhs;
+        while (!__builtin_amdgcn_readfirstlane(T.S.done)) {
+            traj8_advance<CE>(P, K, T, B, atom, kA, qr);
+            ++iters;
+        }
+        if (lane < 8) traj8_store(W, i, T, l);
+        if (lane == 0) {
+            st.rhs += T.S.nrhs;
+            st.acc += T.S.nacc;
+            st.rej += T.S.nrej;
+            st.done += 1;
+            st.useful += T.S.nacc + T.S.nrej - resumed_at;
+            solo_rhs += (uint64_t)(T.S.nrhs - resumed_rhs);
+            solo_done += 1;
+            if (P.stats) {
+                const uint64_t key = longest_key(P, i, T.S.nacc, T.S.nrej);
+                st.longest = key > st.longest ? key : st.longest;
+            }
+        }
+    }
+    flush_stats(P.stats, st, 0ull);
+    if (P.stats && lane == 0) {
+        atomicAdd((unsigned long long*)&P.stats[4], (unsigned long long)iters);
+        atomicAdd((unsigned long long*)&P.stats[8], (unsigned long long)solo_rhs);
+        atomicAdd((unsigned long long*)&P.stats[9], (unsigned long long)solo_done);
+    }
 }
 
 __global__ void k_reset_counters(unsigned long long* q, int n)
@@ -452,11 +509,12 @@ static hipError_t integrate_enqueue(IntegrateCall& c, void* ws, int n_cu, hipStr
         }
         timer.mark(3);
         if (cap2 > 0) {
-            // one wave per block and as many blocks as the chip has SIMDs, so that the survivors
-            // run without wave neighbours and, as the dispatcher spreads them, without SIMD ones
-            const int64_t blocks1 = std::min<int64_t>((int64_t)n_cu * 4, cap2);
+            // one wave per SIMD: blocks of four waves, at most one block per compute unit, so that the
+            // survivors run without wave or SIMD neighbours
+            const int64_t waves1 = std::min<int64_t>((int64_t)n_cu * 4, cap2);
+            const int64_t blocks1 = (waves1 + 3) / 4;
             void* args1[] = {&P, &W, &C2};
-            const hipError_t e1 = hipLaunchKernel(k_solo, dim3((unsigned)blocks1), dim3(64), args1, 0, st);
+            const hipError_t e1 = hipLaunchKernel(k_solo, dim3((unsigned)blocks1), dim3(256), args1, 0, st);
             if (launch_err == hipSuccess) launch_err = e1;
         }
     }
