@@ -46,7 +46,12 @@ def parse():
                          "1.2e7-trajectory 225-cell sweep with per-cell reductions; tangent / adjoint: the 512^2 "
                          "differentiation grid")
     ap.add_argument("--autotune", default="", metavar="CACHE.json",
-                    help="pick block / refill / step budget by timing candidates on 2^16 ids (cached)")
+                    help="cache file of the launch-shape autotuner (stream: it always runs, on the warm-up "
+                         "ids; other workloads: only with this option)")
+    ap.add_argument("--no-autotune", action="store_true", help="stream: keep the default launch shape")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="chunked workloads: launch every chunk eagerly instead of replaying one captured HIP "
+                         "graph per stream")
     ap.add_argument("--chunk", type=int, default=0, help="ids per chunk (default: the job split evenly over the streams)")
     ap.add_argument("--streams", type=int, default=2, help="streams the chunks are spread over")
     ap.add_argument("--n", type=int, default=0, help="run only the first N ids of the workload")
@@ -156,7 +161,7 @@ def chunked_job(api, torch, w, n, args, stats, kernel):
         print(f"[bench] {kernel}: chunk {c + 1}/{nc} done at {time.perf_counter() - t0:.1f} s", file=sys.stderr,
               flush=True)
 
-    res = api.run_chunks(w, n=n, chunk=chunk, n_streams=args.streams, kernel=kernel,
+    res = api.run_chunks(w, n=n, chunk=chunk, n_streams=args.streams, kernel=kernel, graph=not args.no_graph,
                          cells=args.workload in ("sweep", "thermal"),
                          hist=args.workload in ("stream", "stream-chunks", "fig4"), stats=stats,
                          progress=progress)
@@ -268,8 +273,10 @@ def main_stream(args):
     sp = w.species()
     cur = torch.cuda.current_stream()
 
+    launch = {}
+
     def batch(n, id0, out, hist, **kw):
-        api.integrate(w.system, sp, w.gen, n, id0=id0, out=out, counters=False, **kw)
+        api.integrate(w.system, sp, w.gen, n, id0=id0, out=out, counters=False, **launch, **kw)
         api.reduce_hist(w.system, sp, w.gen, n, out, id0=id0, out=hist)
 
     n = K * C
@@ -281,6 +288,10 @@ def main_stream(args):
         wo = {k: v[:m] for k, v in out.items()} if m <= n else api.alloc_obs(m, dev, counters=False)
         batch(m, 0, wo, None)
         del wo
+    if not args.no_autotune:
+        # the main kernel's launch shape, timed on ids of the warm-up range (outside the timed batch)
+        launch = api.autotune(w, n=min(1 << 20, max(id0, 1 << 16)), id0=0, cache=args.autotune or None)
+        print(f"[bench] autotuned launch {launch}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     hist = torch.zeros(len(w.gen.species) * 2 * 64 + 256, dtype=torch.float64, device=dev)
     stats = api.new_stats()
@@ -322,6 +333,7 @@ def main_stream(args):
         "config": {"workload": w.name, "trajectories_in_stream": w.n, "chunk": C, "timed_ids": [id0, id0 + n],
                    "step": "one chunk of 2^22 ids; the K timed chunks integrated as one batch (one refill queue) "
                            "and reduced to on-device histograms", "kernel": "persistent",
+                   "launch": launch or "default",
                    "rtol": w.system.rtol, "atol": w.system.atol, "max_steps": w.system.max_steps,
                    "reductions": "W0 (complex/total over log10(E/W0), per species) and heating histograms"},
         "rk_stages_per_s": s[0] / secs, "accepted_steps_per_s": s[1] / secs,
@@ -349,7 +361,8 @@ def main_stream(args):
             torch.cuda.synchronize()
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record(cur)
-            api.integrate(w.system, sp, w.gen, C, id0=id0, out=o, counters=False, kernel=kern, stats=st)
+            api.integrate(w.system, sp, w.gen, C, id0=id0, out=o, counters=False, kernel=kern, stats=st,
+                          **(launch if kern == "persistent" else {}))
             b.record(cur)
             torch.cuda.synchronize()
             t = a.elapsed_time(b) / 1e3
@@ -656,9 +669,9 @@ def main():
     launch = dict(kernel=args.kernel, block=args.block, blocks_per_cu=args.blocks_per_cu,
                   refill_every=args.refill_every)
     if args.autotune and args.kernel == "persistent":
-        best = api.autotune(w, n=min(w.n, 1 << 16), cache=args.autotune)
+        best = api.autotune(w, n=min(w.n, 1 << 20), cache=args.autotune)
         print(f"[bench] autotuned launch {best}", file=sys.stderr, flush=True)
-        launch.update(block=best["block"], refill_every=best["refill_every"], step_budget=best["step_budget"])
+        launch.update(best)
     r = timed_runs(api, torch, w, out, stats, args.steps, args.warmup, **launch)
     K = args.steps
     traj_s = w.n * K / r["total_s"]

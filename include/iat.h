@@ -136,6 +136,11 @@ typedef struct {
     const int32_t* species;                  /* ARRAYS mode, device, or NULL          */
     const double* y0;                        /* 12 x n start states (a.u.), or NULL:
                                                 overrides the head-on start (any mode) */
+    const int64_t* id0_dev;                  /* device int64, or NULL: added to gen.id0 when the
+                                                kernels run, so that one call captured in a HIP
+                                                graph can be replayed over successive chunks of a
+                                                sweep (the caller keeps grid ids inside the grid;
+                                                BOXCOUNT refuses it)                      */
     iat_gen gen;
 } iat_batch;
 

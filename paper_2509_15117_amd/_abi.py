@@ -49,7 +49,7 @@ class Gen(ctypes.Structure):
 
 class Batch(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("theta", _vp), ("phi", _vp), ("E", _vp), ("q_x", _vp), ("De", _vp),
-                ("phase0", _vp), ("species", _vp), ("y0", _vp), ("gen", Gen)]
+                ("phase0", _vp), ("species", _vp), ("y0", _vp), ("id0_dev", _vp), ("gen", Gen)]
 
 
 class Obs(ctypes.Structure):

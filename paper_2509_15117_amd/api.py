@@ -99,13 +99,17 @@ def obs_struct(out: Dict[str, torch.Tensor]) -> _abi.Obs:
 
 
 def batch_struct(n: int, gen, arrays: Optional[Dict[str, torch.Tensor]] = None,
-                 y0: Optional[torch.Tensor] = None, id0: Optional[int] = None) -> _abi.Batch:
+                 y0: Optional[torch.Tensor] = None, id0: Optional[int] = None,
+                 id0_dev: Optional[torch.Tensor] = None) -> _abi.Batch:
     b = _abi.Batch()
     b.n = int(n)
     arrays = arrays or {}
     for k in ("theta", "phi", "E", "q_x", "De", "phase0", "species"):
         setattr(b, k, _ptr(arrays.get(k)))
     b.y0 = _ptr(y0)
+    if id0_dev is not None and (id0_dev.dtype != torch.int64 or not id0_dev.is_cuda or id0_dev.numel() != 1):
+        raise ValueError("id0_dev must be a device int64 tensor of one element")
+    b.id0_dev = _ptr(id0_dev)
     b.gen = gen_struct(gen, id0)
     return b
 
@@ -151,7 +155,7 @@ def longest_of(stats) -> tuple:
 def integrate(system, species, gen, n: int, *, arrays=None, y0=None, id0=None, kernel="persistent", block=0,
               blocks_per_cu=0, refill_every=0, step_budget=0, y_final=False, counters=True, stats=None, out=None,
               stream=None, device=None, kernel_ms=None, max_suspended=0, tail_budget=0,
-              noalloc=False) -> Dict[str, torch.Tensor]:
+              noalloc=False, id0_dev=None) -> Dict[str, torch.Tensor]:
     """Integrate n trajectories on the current GPU; returns device tensors of the observables.
 
     system / gen: objects with the fields of workloads.System / workloads.Generator.
@@ -160,14 +164,15 @@ def integrate(system, species, gen, n: int, *, arrays=None, y0=None, id0=None, k
     kernel_ms: optional phase_ms() buffer receiving the phase durations (setup, main, tail, solo,
     observables) measured with HIP events on the stream; the call then waits for completion.
     noalloc=True calls iat_integrate_noalloc (the library's fixed workspace; n <= NOALLOC_MAX_N, no
-    kernel_ms; pass `out` to keep the call itself free of allocations)."""
+    kernel_ms; pass `out` to keep the call itself free of allocations).  id0_dev: optional device int64
+    tensor of one element added to the first id when the kernels run (graph replays over chunks)."""
     L = _abi.load()
     device = device or torch.device("cuda", torch.cuda.current_device())
     if out is None:
         out = alloc_obs(n, device, y_final=y_final, counters=counters)
     sysv = system_struct(system)
     sp = species_array(species)
-    b = batch_struct(n, gen, arrays, y0, id0)
+    b = batch_struct(n, gen, arrays, y0, id0, id0_dev)
     o = obs_struct(out)
     la = launch_struct(kernel, block, blocks_per_cu, refill_every, step_budget, stats, kernel_ms, max_suspended,
                        tail_budget)
@@ -222,11 +227,11 @@ def n_cells(gen) -> int:
     return max(1, len(gen.species)) * max(1, len(gen.E_list)) * max(1, len(gen.q_list)) * max(1, len(gen.De_list))
 
 
-def _reduce(kind, system, species, gen, n, obs, out, id0, arrays, stream):
+def _reduce(kind, system, species, gen, n, obs, out, id0, arrays, stream, id0_dev=None):
     L = _abi.load()
     sysv = system_struct(system)
     sp = species_array(species)
-    b = batch_struct(n, gen, arrays, None, id0)
+    b = batch_struct(n, gen, arrays, None, id0, id0_dev)
     o = obs_struct(obs)
     rc = L.iat_reduce(ctypes.byref(sysv), sp, len(species), ctypes.byref(b), ctypes.byref(o), kind, _ptr(out),
                       _stream_handle(stream))
@@ -234,16 +239,17 @@ def _reduce(kind, system, species, gen, n, obs, out, id0, arrays, stream):
     return out
 
 
-def reduce_cells(system, species, gen, n, obs, *, id0=None, arrays=None, out=None, stream=None):
+def reduce_cells(system, species, gen, n, obs, *, id0=None, arrays=None, out=None, stream=None, id0_dev=None):
     """Per sweep cell (count, complex count, sum dE_ion, sum dE_ion^2, sum n_bounce), shape n_cells x 5.
     Passing the previous chunk's out accumulates."""
     dev = obs["status"].device
     if out is None:
         out = torch.zeros(n_cells(gen), 5, dtype=torch.float64, device=dev)
-    return _reduce(_abi.REDUCE_CELLS, system, species, gen, n, obs, out, id0, arrays, stream)
+    return _reduce(_abi.REDUCE_CELLS, system, species, gen, n, obs, out, id0, arrays, stream, id0_dev)
 
 
-def reduce_hist(system, species, gen, n, obs, *, id0=None, arrays=None, out=None, stream=None, flag="complex"):
+def reduce_hist(system, species, gen, n, obs, *, id0=None, arrays=None, out=None, stream=None, flag="complex",
+                id0_dev=None):
     """Complex/total counts over log10(E/W0) per species slot (n_slots x 64 x 2) and the heating histogram
     (256,) in one flat tensor; use split_hist() to view them.  Passing the previous out accumulates.
     flag="bound" counts the trajectories that reached the negative-energy bound state in the second
@@ -253,7 +259,7 @@ def reduce_hist(system, species, gen, n, obs, *, id0=None, arrays=None, out=None
     if out is None:
         out = torch.zeros(slots * 2 * _abi.W0_BINS + _abi.HEAT_BINS, dtype=torch.float64, device=dev)
     kind = {"complex": _abi.REDUCE_W0_HIST, "bound": _abi.REDUCE_W0_HIST_BOUND}[flag]
-    return _reduce(kind, system, species, gen, n, obs, out, id0, arrays, stream)
+    return _reduce(kind, system, species, gen, n, obs, out, id0, arrays, stream, id0_dev)
 
 
 def split_hist(flat: torch.Tensor):
@@ -361,7 +367,7 @@ class ScatteringObservables(torch.autograd.Function):
 
 def run_chunks(w, *, n: Optional[int] = None, chunk: int = 1 << 22, n_streams: int = 4, kernel="persistent",
                cells: bool = False, hist: bool = False, hist_bound: bool = False,
-               stats: Optional[torch.Tensor] = None, progress=None, sample=None, **launch):
+               stats: Optional[torch.Tensor] = None, progress=None, sample=None, graph: bool = False, **launch):
     """Integrate ids [0, n) of a workloads.Workload in chunks of `chunk` ids spread round-robin over
     `n_streams` streams (default priority), reducing each chunk on its stream: per-cell sums (cells=True,
     sweeps), the W0 / heating histograms (hist=True) and the W0 histogram of the bound-state flag
@@ -370,7 +376,11 @@ def run_chunks(w, *, n: Optional[int] = None, chunk: int = 1 << 22, n_streams: i
     Returns {'cells': (n_cells, 5), 'hist': flat histogram} (device tensors, summed over streams).
     progress(c, n_chunks): called on the host as chunk c completes (in chunk order).
     sample: optional sorted global ids whose per-trajectory outputs (with step counters and final
-    states) are copied out of their chunk before its buffers are reused: res['sample']."""
+    states) are copied out of their chunk before its buffers are reused: res['sample'].
+    graph=True: each stream captures its chunk's calls (integration and reductions) once in a HIP graph,
+    with the chunk's first id read from a device scalar (iat_batch.id0_dev), and replays it for every
+    later full chunk after writing that id; the first chunk runs eagerly (code objects, pools) and so
+    does a shorter last chunk.  The bits are those of the eager calls (not with sample)."""
     n = w.n if n is None else n
     dev = torch.device("cuda", torch.cuda.current_device())
     cur = torch.cuda.current_stream()
@@ -393,20 +403,43 @@ def run_chunks(w, *, n: Optional[int] = None, chunk: int = 1 << 22, n_streams: i
                for _ in streams] if hist_bound else None)
     for s in streams:
         s.wait_stream(cur)
+    if graph and want:
+        raise ValueError("run_chunks: graph replay does not copy out samples")
+    offs = [torch.zeros(1, dtype=torch.int64, device=dev) for _ in streams] if graph else None
+    graphs = [None] * len(streams)
+
+    def calls(k, cnt, id0, id0_dev):
+        obs = {key: v[:cnt] for key, v in bufs[k].items()}
+        integrate(w.system, w.species(), w.gen, cnt, id0=id0, out=obs, stream=streams[k], kernel=kernel, stats=stats,
+                  id0_dev=id0_dev, **launch)
+        if cells:
+            reduce_cells(w.system, w.species(), w.gen, cnt, obs, id0=id0, out=c_out[k], stream=streams[k],
+                         id0_dev=id0_dev)
+        if hist:
+            reduce_hist(w.system, w.species(), w.gen, cnt, obs, id0=id0, out=h_out[k], stream=streams[k],
+                        id0_dev=id0_dev)
+        if hist_bound:
+            reduce_hist(w.system, w.species(), w.gen, cnt, obs, id0=id0, out=hb_out[k], stream=streams[k],
+                        flag="bound", id0_dev=id0_dev)
+        return obs
+
     done = []
     for c, id0 in enumerate(range(0, n, chunk)):
         k = c % len(streams)
         cnt = min(chunk, n - id0)
-        obs = {key: v[:cnt] for key, v in bufs[k].items()}
-        integrate(w.system, w.species(), w.gen, cnt, id0=id0, out=obs, stream=streams[k], kernel=kernel, stats=stats,
-                  **launch)
-        if cells:
-            reduce_cells(w.system, w.species(), w.gen, cnt, obs, id0=id0, out=c_out[k], stream=streams[k])
-        if hist:
-            reduce_hist(w.system, w.species(), w.gen, cnt, obs, id0=id0, out=h_out[k], stream=streams[k])
-        if hist_bound:
-            reduce_hist(w.system, w.species(), w.gen, cnt, obs, id0=id0, out=hb_out[k], stream=streams[k],
-                        flag="bound")
+        if graph and c > 0 and cnt == m:
+            with torch.cuda.stream(streams[k]):
+                if graphs[k] is None:
+                    streams[k].synchronize()
+                    g = torch.cuda.CUDAGraph()
+                    with torch.cuda.graph(g, stream=streams[k]):
+                        calls(k, cnt, 0, offs[k])
+                    graphs[k] = g
+                offs[k].fill_(id0)
+                graphs[k].replay()
+            obs = {key: v[:cnt] for key, v in bufs[k].items()}
+        else:
+            obs = calls(k, cnt, id0, None)
         if want:
             a = int(torch.searchsorted(ids_h, torch.tensor(id0)))
             b = int(torch.searchsorted(ids_h, torch.tensor(id0 + cnt)))
@@ -443,46 +476,75 @@ def run_chunks(w, *, n: Optional[int] = None, chunk: int = 1 << 22, n_streams: i
         for v in b.values():
             for s in streams:
                 v.record_stream(s)
+    if graph:
+        for o in offs:
+            for s in streams:
+                o.record_stream(s)
+        res["graphs"] = graphs   # keep the captured graphs (and their memory) alive with the results
     return res
 
 
-def autotune(w, *, n: int = 1 << 16, cache: Optional[str] = None, budgets=(1, 5000, 20000, 80000),
-             blocks=(128, 256), refills=(1, 4, 16), verbose: bool = False) -> Dict[str, int]:
-    """Pick the persistent kernel's launch shape (block size, refill granularity, step budget; a budget of
-    1 hands every trajectory to the four-lanes-per-trajectory kernel, 16 per wave, instead of one lane
-    each) for a workload by timing each candidate on its first n ids (HIP events on the current stream), and
-    cache the winner in a JSON file keyed by the workload name and n.  Returns keyword arguments for
-    integrate() / run_chunks().  Every candidate gives the same bits; only the time differs."""
+def autotune(w, *, n: int = 1 << 20, id0: int = 0, cache: Optional[str] = None, blocks=(64, 128, 256),
+             refills=(1, 4, 16, 64), blocks_per_cu=(0, 1), step_budget: int = 20000,
+             verbose: bool = False) -> Dict[str, int]:
+    """Pick the persistent kernel's launch shape for a workload (block size, refill granularity,
+    resident blocks per compute unit; 0 = as many as fit) by the main kernel's throughput: the RHS
+    evaluations it performed over its event-timed duration.  The sample is ids [id0, id0 + n) of a
+    random sweep (independent draws), or for a grid n / 16 ids at each of 16 places spread over it.
+    For these runs the accepted-step cap is lowered to twice the step budget, so the latency-bound
+    four-lane and solo levels, which the shape does not change, stay short; the main kernel's work up
+    to the budget is the same.  The winner is cached in a JSON file keyed by the workload, n and the
+    budget.  Returns keyword arguments for integrate() / run_chunks(); every candidate gives the same
+    bits, only the time differs."""
+    import copy
     import json
     import os
-    key = f"{w.name}:{n}"
+    key = f"{w.name}:{n}:{step_budget}"
     if cache and os.path.exists(cache):
         try:
             with open(cache) as f:
                 hit = json.load(f).get(key)
             if hit:
-                return {k: v for k, v in hit.items() if k != "ms"}
-        except (OSError, ValueError):
+                return {k: v for k, v in hit.items() if k in ("block", "refill_every", "blocks_per_cu", "step_budget")}
+        except (OSError, ValueError, AttributeError):
             pass
+    wt = copy.deepcopy(w)
+    wt.system.max_steps = 2 * step_budget
+    if w.gen.kind == "grid":
+        total = int(w.gen.n_theta) * int(w.gen.n_phi)
+        parts = 16 if total >= 16 else 1
+        m = max(1, min(n, total) // parts)
+        starts = [(total - m) * k // max(parts - 1, 1) for k in range(parts)]
+    else:
+        m, starts = n, [id0]
     dev = torch.device("cuda", torch.cuda.current_device())
-    out = alloc_obs(n, dev, counters=False)
-    stream = torch.cuda.current_stream()
-    best, best_t = None, float("inf")
-    integrate_workload(w, n=n, out=out)          # warm-up (code objects, pools)
+    out = alloc_obs(m, dev, counters=False)
+    stats = new_stats(dev)
+
+    def rate(cfg):
+        stats.zero_()
+        main_ms = 0.0
+        for s0 in starts:
+            ms = phase_ms()
+            integrate_workload(wt, n=m, id0=s0, out=out, stats=stats, kernel_ms=ms, kernel="persistent",
+                               step_budget=step_budget, **cfg)
+            main_ms += ms[1]
+        st = stats.cpu().tolist()
+        return (st[0] - st[6] - st[8]) / max(main_ms * 1e-3, 1e-9), main_ms
+
+    rate(dict(block=256, refill_every=1, blocks_per_cu=0))          # warm-up (code objects, pools)
+    best, best_r, table = None, -1.0, []
     for blk in blocks:
         for rf in refills:
-            for bud in budgets:
-                cfg = dict(kernel="persistent", block=blk, refill_every=rf, step_budget=bud)
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                integrate_workload(w, n=n, out=out, **cfg)
-                e1.record(stream)
-                e1.synchronize()
-                t = e0.elapsed_time(e1)
+            for pc in blocks_per_cu:
+                cfg = dict(block=blk, refill_every=rf, blocks_per_cu=pc)
+                r, main_ms = rate(cfg)
+                table.append(dict(cfg, rhs_per_s=r, main_ms=main_ms))
                 if verbose:
-                    print(f"autotune {key}: {cfg} {t:.1f} ms", flush=True)
-                if t < best_t:
-                    best, best_t = cfg, t
+                    print(f"autotune {key}: {cfg} main kernel {main_ms:.1f} ms, {r:.3e} RHS/s", flush=True)
+                if r > best_r:
+                    best, best_r = cfg, r
+    best = dict(best, step_budget=step_budget)
     if cache:
         data = {}
         if os.path.exists(cache):
@@ -491,7 +553,7 @@ def autotune(w, *, n: int = 1 << 16, cache: Optional[str] = None, budgets=(1, 50
                     data = json.load(f)
             except (OSError, ValueError):
                 data = {}
-        data[key] = dict(best, ms=best_t)
+        data[key] = dict(best, rhs_per_s=best_r, candidates=table)
         os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
         with open(cache, "w") as f:
             json.dump(data, f, indent=1)

@@ -184,6 +184,7 @@ void fill_params(KParams& P, const iat_system* sys, const iat_species* species, 
     P.phase_arr = batch->phase0;
     P.sp_arr = batch->species;
     P.y0 = batch->y0;
+    P.id0_dev = batch->id0_dev;
     P.gen = batch->gen;
 }
 

@@ -85,6 +85,7 @@ struct KParams {
     int64_t n;
     const double *theta, *phi, *E_arr, *qx_arr, *De_arr, *phase_arr, *y0;
     const int32_t* sp_arr;
+    const int64_t* id0_dev;      // device offset added to gen.id0, or NULL
     iat_gen gen;
     // outputs
     double *angle, *q_transfer, *dE_ion, *t_dwell, *t_first, *t_last;
@@ -162,10 +163,14 @@ __device__ __forceinline__ void philox4x64(uint64_t c[4], uint64_t k0, uint64_t 
 
 __device__ __forceinline__ double unit_double(uint64_t x) { return (double)(x >> 11) * 0x1.0p-53; }
 
+// Global id of the batch's first trajectory: gen.id0, plus the device-side offset when one is given
+// (one captured call replayed over successive chunks).
+__device__ __forceinline__ int64_t batch_id0(const KParams& P) { return P.gen.id0 + (P.id0_dev ? *P.id0_dev : 0); }
+
 // Trajectory id -> physical parameters (GRID / SWEEP / ARRAYS generators, see iat.h).
 __device__ inline void traj_params(const KParams& P, int64_t i, TrajParams& t)
 {
-    const int64_t gid = P.gen.id0 + i;
+    const int64_t gid = batch_id0(P) + i;
     double theta = 0.0, phi = 0.0;
     t.E = P.E;
     t.qx = P.q_x;
@@ -241,7 +246,7 @@ __device__ inline void start_state_au(const KParams& P, int64_t i, const TrajPar
     }
     if (P.gen.kind == IAT_GEN_THERMAL) {
         double z[10];
-        thermal_normals(P, P.gen.id0 + i, z);
+        thermal_normals(P, batch_id0(P) + i, z);
         const double n0 = t.sin_t * t.cos_p, n1 = t.sin_t * t.sin_p, n2 = t.cos_t;
         const double sa = sqrt(t.E / species_mass(P, t.sp));
         double v0 = sa * z[0], v1 = sa * z[1], v2 = sa * z[2];

@@ -52,7 +52,7 @@ __device__ __forceinline__ uint64_t longest_key(const KParams& P, int64_t i, int
 {
     int64_t steps = (int64_t)nacc + (int64_t)nrej;
     steps = steps < 0 ? 0 : (steps > 0x3fffffff ? 0x3fffffff : steps);
-    const int64_t gid = (P.gen.kind == IAT_GEN_ARRAYS ? 0 : P.gen.id0) + i;
+    const int64_t gid = (P.gen.kind == IAT_GEN_ARRAYS ? 0 : batch_id0(P)) + i;
     return ((uint64_t)steps << 34) | ((uint64_t)gid & 0x3ffffffffull);
 }
 

@@ -29,6 +29,7 @@ struct RedIn {
     const int32_t* nb;
     const uint32_t* status;
     int64_t n, id0;
+    const int64_t* id0_dev;      // device offset added to id0, or NULL
     const double *t_first, *t_last;
 };
 
@@ -50,7 +51,8 @@ __global__ void k_reduce_cells(KParams P, RedIn R, double* part, int64_t ncell)
     if (t >= ncell * kSlices) return;
     const int64_t c = t / kSlices, j = t % kSlices;
     // local index i has global id id0 + i and cell (id0 + i) mod ncell
-    int64_t first = (c - R.id0 % ncell + ncell) % ncell;     // smallest local i of cell c
+    const int64_t id0 = R.id0 + (R.id0_dev ? *R.id0_dev : 0);
+    int64_t first = (c - id0 % ncell + ncell) % ncell;       // smallest local i of cell c
     const int64_t per = (R.n + kSlices - 1) / kSlices;
     const int64_t lo = j * per, hi = min(R.n, lo + per);
     int64_t i = first;
@@ -273,8 +275,8 @@ extern "C" int iat_reduce(const iat_system* sys, const iat_species* species, int
         return set_error(IAT_EINVAL, "reduce: obs.dE_ion, obs.n_bounce and obs.status are required");
     KParams P;
     fill_params(P, sys, species, n_species, batch);
-    RedIn R{obs->dE_ion, obs->n_bounce, obs->status, batch->n, batch->gen.id0, obs->t_bounce_first,
-            obs->t_bounce_last};
+    RedIn R{obs->dE_ion, obs->n_bounce, obs->status, batch->n, batch->gen.id0, batch->id0_dev,
+            obs->t_bounce_first, obs->t_bounce_last};
     hipStream_t st = (hipStream_t)stream;
     if (batch->n == 0) return 0;
     if (kind == IAT_REDUCE_CELLS) {
@@ -306,7 +308,7 @@ extern "C" int iat_reduce(const iat_system* sys, const iat_species* species, int
         hipLaunchKernelGGL(k_life_fit, dim3(1), dim3(64), 0, st, out, nsp);
     } else if (kind == IAT_REDUCE_BOXCOUNT) {
         const iat_gen& g = batch->gen;
-        if (g.kind != IAT_GEN_GRID || g.id0 != 0 || batch->n != (int64_t)g.n_theta * g.n_phi)
+        if (g.kind != IAT_GEN_GRID || g.id0 != 0 || batch->id0_dev || batch->n != (int64_t)g.n_theta * g.n_phi)
             return set_error(IAT_EINVAL, "reduce BOXCOUNT needs a whole GRID batch");
         const int nt = g.n_theta, npp = g.n_phi;
         if (nt != npp || nt < 2 || (nt & (nt - 1)) != 0 || nt > 32768)

@@ -33,6 +33,9 @@ def test_struct_layouts_match_header_sizes():
     assert ctypes.sizeof(_abi.Gen) == 64 + 8 * 30 + 16 + 8
     assert ctypes.sizeof(_abi.Obs) == 12 * 8
     assert ctypes.sizeof(_abi.Launch) == 8 * 4 + 8 * 2
+    # n, seven per-trajectory arrays, y0 and the device-side id offset, then the generator
+    assert ctypes.sizeof(_abi.Batch) == 8 + 9 * 8 + ctypes.sizeof(_abi.Gen)
+    assert _abi.Batch.gen.offset == 80 and _abi.Batch.id0_dev.offset == 72
 
 
 def _call(system=None, species=None, n_species=None, batch=None, obs=None, launch=None):
@@ -186,3 +189,16 @@ def test_noalloc_refuses_oversized_batches_and_timing_without_gpu():
     la = api.launch_struct(block=100)
     rc, msg = call(4, la)
     assert rc == _abi.IAT_EINVAL and "block" in msg, msg
+
+
+def test_boxcount_refuses_a_device_id_offset_without_gpu():
+    """Box counting needs the whole grid from id 0; a batch whose first id is only known on the device
+    (graph replays over chunks) is refused before the GPU is touched."""
+    from paper_2509_15117_amd import api
+    L = _abi.load()
+    w = W.config1()
+    b = api.batch_struct(64, w.gen)
+    b.id0_dev = 0x1000                               # never dereferenced: refused first
+    rc = L.iat_reduce(ctypes.byref(api.system_struct(w.system)), api.species_array(w.species()), 1, ctypes.byref(b),
+                      ctypes.byref(_obs_dummy()), _abi.REDUCE_BOXCOUNT, ctypes.c_void_p(0x1000), None)
+    assert rc == _abi.IAT_EINVAL and "BOXCOUNT" in L.iat_last_error().decode()

@@ -49,3 +49,31 @@ def test_graph_replays_match_eager():
         assert torch.equal(cells, cells_eager), r
     hw, hh = api.split_hist(cells)
     assert float(hw[..., 0].sum()) == n and float(hh.sum()) == n
+
+
+@pytest.mark.parametrize("which", ["sweep", "stream"])
+def test_run_chunks_graph_replays_match_eager_chunks(which):
+    """The chunked driver with graph replay: per stream one captured call sequence (integration and
+    reductions) whose first id is read from a device scalar, replayed for every later full chunk.
+    Per-cell sums, both W0 histograms and the counters must equal those of eager calls bit for bit
+    (each chunk's work is integers and fixed-order sums), over several replays per stream and a
+    shorter last chunk."""
+    w = W.config3() if which == "sweep" else W.config5()
+    w.system.max_steps = 200_000
+    n, chunk = 5 * 6000 + 1234, 6000
+    kw = dict(n=n, chunk=chunk, n_streams=2, cells=which == "sweep", hist=True, hist_bound=which == "stream")
+    print(f"graph: run_chunks {which}, n={n}, chunk={chunk}", flush=True)
+    s_e, s_g = api.new_stats(), api.new_stats()
+    eager = api.run_chunks(w, stats=s_e, **kw)
+    torch.cuda.synchronize()
+    replay = api.run_chunks(w, stats=s_g, graph=True, **kw)
+    torch.cuda.synchronize()
+    assert replay["graphs"][0] is not None and replay["graphs"][1] is not None
+    for key in ("cells", "hist", "hist_bound"):
+        if key in eager:
+            assert torch.equal(eager[key], replay[key]), key
+    a, b = s_e.cpu().tolist(), s_g.cpu().tolist()
+    for j in (0, 1, 2, 3, 5, 6, 7, 8, 9, 10):
+        assert a[j] == b[j], (j, a, b)
+    hw, _ = api.split_hist(replay["hist"])
+    assert float(hw[..., 0].sum()) == n
