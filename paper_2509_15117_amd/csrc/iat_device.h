@@ -326,11 +326,15 @@ __device__ __forceinline__ double dot3(double a0, double a1, double a2, double b
 // the atom is F = s d with s = 8 C8' u^5 - 4 C4' u^3; atom acceleration F/m_a; ion acceleration
 // -F/m_i - kappa_k r_i,k with kappa_k = (a_k + 2 q_k cos(tau + phase0))/4 = kA_k + qc qr_k,
 // qc = (q_x/2) cos(tau + phase0).
-__device__ __forceinline__ double force_scale(const Lane& L, double d0, double d1, double d2)
+__device__ __forceinline__ double force_scale_rr(const Lane& L, double rr)
 {
-    const double u = recip(dot3(d0, d1, d2, d0, d1, d2));
+    const double u = recip(rr);
     const double u2 = u * u;
     return u2 * u * (L.c8x8 * u2 - L.c4x4);
+}
+__device__ __forceinline__ double force_scale(const Lane& L, double d0, double d1, double d2)
+{
+    return force_scale_rr(L, dot3(d0, d1, d2, d0, d1, d2));
 }
 __device__ __forceinline__ double acc_atom(const Lane& L, double s, double dk) { return (s * dk) * L.inv_ma; }
 __device__ __forceinline__ double acc_ion(double inv_mi, double s, double dk, double kA, double qc, double qr,
@@ -1368,95 +1372,203 @@ __device__ __forceinline__ int oct_or(int v)
     return quad_or(v | __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false));
 }
 
-// Stage cosines for the eight-lane form: the values of stage_cos, with lanes 0..5 each evaluating one
-// of the six small-angle series (lane 0 the phase remainder, lanes 1..5 the offsets c2 h, c3 h, c4 h,
-// c5 h and h) in a single round, gathered with row broadcasts.
-__device__ __forceinline__ StageCos stage_cos8(double tau, double phase0, double h, const Tab& T)
+// Per-lane constants of the eight-lane form, set once per kernel and held in registers.
+struct Oct {
+    bool atom;        // lanes 0..3: the atom's side of the half-row mirror
+    bool l0;          // lane 0: evaluates the series of the phase remainder
+    double kA, qr;    // this lane's axis k: a_k / 4 and q_k / q_x
+    double cl;        // lanes 1..5: the offset coefficient c2, c3, c4, c5, 1 of this lane's stage series
+};
+__device__ __forceinline__ Oct oct_consts(const KParams& P, const Tab& T)
 {
-    const int l = oct_lane();
-    const double cl = l == 1 ? T.c2 : (l == 2 ? T.c3 : (l == 3 ? T.c4 : (l == 4 ? T.c5 : 1.0)));
+    const int l = oct_lane(), ax = oct_axis();
+    Oct O;
+    O.atom = l < 4;
+    O.l0 = l == 0;
+    O.kA = ax == 0 ? P.kA[0] : (ax == 1 ? P.kA[1] : P.kA[2]);
+    O.qr = ax == 0 ? P.q_ratio[0] : (ax == 1 ? P.q_ratio[1] : P.q_ratio[2]);
+    O.cl = l == 1 ? T.c2 : (l == 2 ? T.c3 : (l == 3 ? T.c4 : (l == 4 ? T.c5 : 1.0)));
+    // opaque values: the compiler keeps them in registers instead of re-deriving them per step
+    asm volatile("" : "+v"(O.kA), "+v"(O.qr), "+v"(O.cl));
+    return O;
+}
+
+// Stage cosines for the eight-lane form: the values of stage_cos.  Lanes 0..5 each evaluate one of the
+// six small-angle series in a single round (lane 0 the phase remainder, lanes 1..5 the offsets c2 h,
+// c3 h, c4 h, c5 h and h); the quadrant of lane 0's result goes to every lane, each of lanes 1..5
+// combines it with its own offset, and row broadcasts gather the five cosines.
+__device__ __forceinline__ StageCos stage_cos8(double tau, double phase0, double h, const Oct& O)
+{
     double k;
     const double r = phase_reduce(tau + phase0, k);
     asm volatile("" ::"v"(r));
-    const double a = l == 0 ? r : cl * h;
+    const double a = O.l0 ? r : O.cl * h;
     double c, s;
     small_sincos(a, c, s);
     double sb, cb;
     phase_quadrant(k, quad_bcast<0, true>(c), quad_bcast<0, true>(s), sb, cb);
+    const double cs = cos_comb(cb, sb, c, s);
     StageCos C;
-    C.c2 = cos_comb(cb, sb, quad_bcast<1, true>(c), quad_bcast<1, true>(s));
-    C.c3 = cos_comb(cb, sb, quad_bcast<2, true>(c), quad_bcast<2, true>(s));
-    C.c4 = cos_comb(cb, sb, quad_bcast<3, true>(c), quad_bcast<3, true>(s));
-    C.c5 = cos_comb(cb, sb, quad_bcast<4, true>(c), quad_bcast<4, true>(s));
-    C.c6 = cos_comb(cb, sb, quad_bcast<5, true>(c), quad_bcast<5, true>(s));
+    C.c2 = quad_bcast<1, true>(cs);
+    C.c3 = quad_bcast<2, true>(cs);
+    C.c4 = quad_bcast<3, true>(cs);
+    C.c5 = quad_bcast<4, true>(cs);
+    C.c6 = quad_bcast<5, true>(cs);
     return C;
 }
 
-// Acceleration of this lane's coordinate at stage position X (negated on ion lanes), by the
-// expressions of acc_atom and acc_ion: d_k = X + partner is X_atom,k - X_ion,k in every lane.
-__device__ __forceinline__ double accel8(const KParams& P, const Lane& L, bool atom, double kA, double qr,
-                                         double cs, double X)
+// Separation at a stage position X (negated on ion lanes): this lane's component d_k = X + partner,
+// the three components in every lane and |d|^2 by the expression of the other forms.
+struct Sep8 {
+    double dk, d0, d1, d2, rr;
+};
+__device__ __forceinline__ Sep8 sep8(double X)
 {
-    const double dk = X + oct_partner(X);
-    const double d0 = quad_bcast<0, true>(dk), d1 = quad_bcast<1, true>(dk), d2 = quad_bcast<2, true>(dk);
-    const double s = force_scale(L, d0, d1, d2);
-    const double qc = L.qx_half * cs;
-    const double aa = acc_atom(L, s, dk);
-    const double ai = acc_ion(P.inv_mi, s, dk, kA, qc, qr, -X);
-    return atom ? aa : -ai;
+    Sep8 D;
+    D.dk = X + oct_partner(X);
+    D.d0 = quad_bcast<0, true>(D.dk);
+    D.d1 = quad_bcast<1, true>(D.dk);
+    D.d2 = quad_bcast<2, true>(D.dk);
+    D.rr = dot3(D.d0, D.d1, D.d2, D.d0, D.d1, D.d2);
+    return D;
 }
 
-// One attempted step (or secant iterate) of the eight-lane form.
+// Acceleration of this lane's coordinate at stage position X with separation D, by the expressions of
+// acc_atom and acc_ion.
+__device__ __forceinline__ double accel8(const KParams& P, const Lane& L, const Oct& O, double cs, double X,
+                                         const Sep8& D)
+{
+    const double s = force_scale_rr(L, D.rr);
+    const double qc = L.qx_half * cs;
+    const double aa = acc_atom(L, s, D.dk);
+    const double ai = acc_ion(P.inv_mi, s, D.dk, O.kA, qc, O.qr, -X);
+    return O.atom ? aa : -ai;
+}
+__device__ __forceinline__ double accel8(const KParams& P, const Lane& L, const Oct& O, double cs, double X)
+{
+    return accel8(P, L, O, cs, X, sep8(X));
+}
+
+// Everything a step of the eight-lane form computes before its bookkeeping: the fifth-order state, the
+// acceleration there (FSAL; not in secant mode), the error norm and the geometry of the new state.
+// SECANT: the step may be a secant iterate (then `exiting` says whether it is); without it the
+// error-norm part runs unconditionally.
+struct Step8 {
+    double x5, v5, F7, en;
+    bool finite;
+    double rho_new, s_new, ww, e_prev, e_new, se_new;
+};
+template <bool CE, bool SECANT>
+__device__ __forceinline__ Step8 traj8_trial(const KParams& P, const StepK& K, const Traj8& T, const Tab& B,
+                                             const Oct& O, double h, bool exiting)
+{
+    const double hh = h * h;
+    const StageCos C = stage_cos8(T.S.tau, T.L.phase0, h, O);
+    const double F2 = accel8(P, T.L, O, C.c2, stage2(T.x, T.v, h, B));
+    const double F3 = accel8(P, T.L, O, C.c3, stage3(T.x, T.v, h, hh, T.F1, B));
+    const double F4 = accel8(P, T.L, O, C.c4, stage4(T.x, T.v, h, hh, T.F1, F2, B));
+    const double F5 = accel8(P, T.L, O, C.c5, stage5(T.x, T.v, h, hh, T.F1, F2, F3, B));
+    const double F6 = accel8(P, T.L, O, C.c6, stage6(T.x, T.v, h, hh, T.F1, F2, F3, F4, B));
+    Step8 R;
+    R.x5 = sol_x(T.x, T.v, h, hh, T.F1, F2, F3, F4, F5, B);
+    R.v5 = sol_v(T.v, h, T.F1, F3, F4, F5, F6, B);
+    const Sep8 D = sep8(R.x5);
+    R.en = 0.0;
+    R.F7 = 0.0;
+    R.finite = true;
+    if (!SECANT || cond<true>(!exiting)) {
+        R.F7 = accel8(P, T.L, O, C.c6, R.x5, D);
+        const double rx = err_ratio(err_x(hh, T.F1, F2, F3, F4, F5, F6, B), T.x, R.x5, K.rtol, K.atol);
+        const double rv = err_ratio(err_v(h, T.F1, F3, F4, F5, F6, R.F7, B), T.v, R.v5, K.rtol, K.atol);
+        // every octet of the wave holds the same trajectory: a wave ballot is the octet's OR
+        const bool bad = cond<true>(ratio_bad(rx) || ratio_bad(rv));
+        const bool nonfin = cond<true>(!(is_finite(R.x5) && is_finite(R.v5)));
+        const double m = oct_max(fmax(rx, rv));
+        R.en = bad ? __builtin_nan("") : m;
+        R.finite = !nonfin;
+    }
+    const double wk = R.v5 + oct_partner(R.v5);
+    const double w0 = quad_bcast<0, true>(wk), w1 = quad_bcast<1, true>(wk), w2 = quad_bcast<2, true>(wk);
+    R.rho_new = D.rr;
+    R.s_new = dot3(D.d0, D.d1, D.d2, w0, w1, w2);
+    R.ww = dot3(w0, w1, w2, w0, w1, w2);
+    R.e_prev = R.e_new = R.se_new = 0.0;
+    if (CE) {
+        const double p0 = quad_bcast<0, true>(T.x), p1 = quad_bcast<1, true>(T.x), p2 = quad_bcast<2, true>(T.x);
+        const double a0 = quad_bcast<0, true>(R.x5), a1 = quad_bcast<1, true>(R.x5), a2 = quad_bcast<2, true>(R.x5);
+        const double u0 = quad_bcast<0, true>(R.v5), u1 = quad_bcast<1, true>(R.v5), u2 = quad_bcast<2, true>(R.v5);
+        R.e_prev = dot3(p0, p1, p2, p0, p1, p2);
+        R.e_new = dot3(a0, a1, a2, a0, a1, a2);
+        R.se_new = dot3(a0, a1, a2, u0, u1, u2);
+    }
+    return R;
+}
+
+// Bookkeeping of the eight-lane form: the shared epilogue and the state update it decides.
 template <bool CE>
-__device__ __forceinline__ void traj8_advance(const KParams& P, const StepK& K, Traj8& T, const Tab& B, bool atom,
-                                              double kA, double qr)
+__device__ __forceinline__ void traj8_finish(const StepK& K, Traj8& T, double h, bool fin, const Step8& R)
+{
+    const StepOutcome o = step_epilogue<CE, true>(K, T.S, T.L, h, fin, R.en, R.finite, R.rho_new, R.s_new, R.ww,
+                                                  R.e_prev, R.e_new, R.se_new);
+    const bool moved = o == OUT_SECANT_DONE || o == OUT_STOP_RFLOOR || o == OUT_ACCEPT || o == OUT_TMAX;
+    T.x = moved ? R.x5 : T.x;
+    T.v = moved ? R.v5 : T.v;
+    T.F1 = (o == OUT_ACCEPT || o == OUT_TMAX) ? R.F7 : T.F1;
+}
+
+// One attempted step (or secant iterate) of the eight-lane form, any mode.
+template <bool CE>
+__device__ __forceinline__ void traj8_advance(const KParams& P, const StepK& K, Traj8& T, const Tab& B, const Oct& O)
 {
     double h;
     bool fin;
     if (!step_prologue<true>(K, T.S, h, fin)) return;
-    const bool exiting = T.S.mode != 0;
-    const double hh = h * h;
-    const StageCos C = stage_cos8(T.S.tau, T.L.phase0, h, B);
-    const double F2 = accel8(P, T.L, atom, kA, qr, C.c2, stage2(T.x, T.v, h, B));
-    const double F3 = accel8(P, T.L, atom, kA, qr, C.c3, stage3(T.x, T.v, h, hh, T.F1, B));
-    const double F4 = accel8(P, T.L, atom, kA, qr, C.c4, stage4(T.x, T.v, h, hh, T.F1, F2, B));
-    const double F5 = accel8(P, T.L, atom, kA, qr, C.c5, stage5(T.x, T.v, h, hh, T.F1, F2, F3, B));
-    const double F6 = accel8(P, T.L, atom, kA, qr, C.c6, stage6(T.x, T.v, h, hh, T.F1, F2, F3, F4, B));
-    const double x5 = sol_x(T.x, T.v, h, hh, T.F1, F2, F3, F4, F5, B);
-    const double v5 = sol_v(T.v, h, T.F1, F3, F4, F5, F6, B);
-    double en = 0.0, F7 = 0.0;
-    bool finite = true;
-    if (cond<true>(!exiting)) {
-        F7 = accel8(P, T.L, atom, kA, qr, C.c6, x5);
-        const double rx = err_ratio(err_x(hh, T.F1, F2, F3, F4, F5, F6, B), T.x, x5, K.rtol, K.atol);
-        const double rv = err_ratio(err_v(h, T.F1, F3, F4, F5, F6, F7, B), T.v, v5, K.rtol, K.atol);
-        const int bad = oct_or((ratio_bad(rx) || ratio_bad(rv)) ? 1 : 0);
-        const int nonfin = oct_or((is_finite(x5) && is_finite(v5)) ? 0 : 1);
-        const double m = oct_max(fmax(rx, rv));
-        en = bad ? __builtin_nan("") : m;
-        finite = nonfin == 0;
+    const Step8 R = traj8_trial<CE, true>(P, K, T, B, O, h, T.S.mode != 0);
+    traj8_finish<CE>(K, T, h, fin, R);
+}
+
+// Steps of the eight-lane form, the common case in a loop of its own.  Almost every step is an ordinary
+// one (stepping mode, under the step cap, not the final step, h above its floor) that is accepted with
+// nothing crossed (no periapsis inside r_b, no separation floor, no exit crossing); for it the
+// prologue and epilogue reduce to one uniform test each and the plain update below, which is what
+// step_prologue and step_epilogue do in that case.  The first step that is not such a step goes
+// through the general path and ends the call.  `iters` counts the attempted steps (and stops).
+template <bool CE>
+__device__ __forceinline__ void traj8_run(const KParams& P, const StepK& K, Traj8& T, const Tab& B, const Oct& O,
+                                          uint64_t& iters)
+{
+    Scal& S = T.S;
+    for (;;) {
+        ++iters;
+        const bool plain = S.mode == 0 && S.nacc < K.max_steps && !(S.h >= K.tau_max - S.tau) && !(S.h < K.hmin);
+        if (!cond<true>(plain)) {
+            traj8_advance<CE>(P, K, T, B, O);
+            return;
+        }
+        const double h = S.h;
+        const Step8 R = traj8_trial<CE, false>(P, K, T, B, O, h, false);
+        const double ex_prev = CE ? R.e_prev : S.rho_prev, ex_new = CE ? R.e_new : R.rho_new;
+        const bool bounce =
+            S.s_prev < 0.0 && R.s_new >= 0.0 && fmin(S.rho_prev, R.rho_new) < T.L.rm2 * K.rb_ratio2;
+        const bool floor = R.rho_new < 0.01 * T.L.rm2;
+        const bool crossing = ex_prev <= K.r0sq && ex_new > K.r0sq && (CE ? R.se_new : R.s_new) > 0.0;
+        const bool quiet = R.en <= 1.0 && R.finite && !bounce && !floor && !crossing;
+        if (!cond<true>(quiet)) {
+            traj8_finish<CE>(K, T, h, false, R);
+            return;
+        }
+        S.nrhs += 6;
+        S.nacc++;
+        S.status |= bound_state(T.L, R.rho_new, R.ww) ? (uint32_t)IAT_ST_BOUND_SEEN : 0u;
+        S.tau = S.tau + h;
+        S.rho_prev = R.rho_new;
+        S.s_prev = R.s_new;
+        S.h = fmin(K.hmax, h * step_factor(R.en, S.last_rej != 0));
+        S.last_rej = 0;
+        T.x = R.x5;
+        T.v = R.v5;
+        T.F1 = R.F7;
     }
-    const double dk = x5 + oct_partner(x5), wk = v5 + oct_partner(v5);
-    const double d0 = quad_bcast<0, true>(dk), d1 = quad_bcast<1, true>(dk), d2 = quad_bcast<2, true>(dk);
-    const double w0 = quad_bcast<0, true>(wk), w1 = quad_bcast<1, true>(wk), w2 = quad_bcast<2, true>(wk);
-    const double rho_new = dot3(d0, d1, d2, d0, d1, d2);
-    const double s_new = dot3(d0, d1, d2, w0, w1, w2);
-    const double ww = dot3(w0, w1, w2, w0, w1, w2);
-    double e_prev = 0.0, e_new = 0.0, se_new = 0.0;
-    if (CE) {
-        const double p0 = quad_bcast<0, true>(T.x), p1 = quad_bcast<1, true>(T.x), p2 = quad_bcast<2, true>(T.x);
-        const double a0 = quad_bcast<0, true>(x5), a1 = quad_bcast<1, true>(x5), a2 = quad_bcast<2, true>(x5);
-        const double u0 = quad_bcast<0, true>(v5), u1 = quad_bcast<1, true>(v5), u2 = quad_bcast<2, true>(v5);
-        e_prev = dot3(p0, p1, p2, p0, p1, p2);
-        e_new = dot3(a0, a1, a2, a0, a1, a2);
-        se_new = dot3(a0, a1, a2, u0, u1, u2);
-    }
-    const StepOutcome o =
-        step_epilogue<CE, true>(K, T.S, T.L, h, fin, en, finite, rho_new, s_new, ww, e_prev, e_new, se_new);
-    const bool moved = o == OUT_SECANT_DONE || o == OUT_STOP_RFLOOR || o == OUT_ACCEPT || o == OUT_TMAX;
-    T.x = moved ? x5 : T.x;
-    T.v = moved ? v5 : T.v;
-    T.F1 = (o == OUT_ACCEPT || o == OUT_TMAX) ? F7 : T.F1;
 }
 
 // A record of the continuation layout (cont_save) into the eight-lane form.

@@ -302,12 +302,11 @@ __global__ void __launch_bounds__(256) k_integrate_solo(KParams P, Work W, Cont 
     const int l = lane & 7;
     const bool atom = l < 4;
     const int ax = atom ? min(l, 2) : min(7 - l, 2);
-    const double kA = ax == 0 ? P.kA[0] : (ax == 1 ? P.kA[1] : P.kA[2]);
-    const double qr = ax == 0 ? P.q_ratio[0] : (ax == 1 ? P.q_ratio[1] : P.q_ratio[2]);
     const unsigned long long cnt = *C.count;
     const int64_t total = (int64_t)(cnt < (unsigned long long)C.cap ? cnt : (unsigned long long)C.cap);
     const Tab B = tab_in_registers();
     const StepK K = step_k_in_registers(P);
+    const Oct O = oct_consts(P, B);
     LaneStats st;
     uint64_t iters = 0, solo_rhs = 0, solo_done = 0;
     for (;;) {
@@ -319,10 +318,7 @@ __global__ void __launch_bounds__(256) k_integrate_solo(KParams P, Work W, Cont 
         int64_t i;
         cont_load8(W, C, (int64_t)slot, atom, ax, T, i);
         const int32_t resumed_at = T.S.nacc + T.S.nrej, resumed_rhs = T.S.nrhs;
-        while (!__builtin_amdgcn_readfirstlane(T.S.done)) {
-            traj8_advance<CE>(P, K, T, B, atom, kA, qr);
-            ++iters;
-        }
+        while (!__builtin_amdgcn_readfirstlane(T.S.done)) traj8_run<CE>(P, K, T, B, O, iters);
         if (lane < 8) traj8_store(W, i, T, l);
         if (lane == 0) {
             st.rhs += T.S.nrhs;
