@@ -416,8 +416,25 @@ __device__ __forceinline__ double err_ratio(double e, double y, double y5, doubl
 __device__ __forceinline__ bool ratio_bad(double r) { return !(r <= 1.0e300); }
 __device__ __forceinline__ bool is_finite(double x) { return __builtin_isfinite(x); }
 
+// fma(a, b, c); A3: as the three-address instruction.  For a chain whose addends are constants kept in
+// registers the compiler otherwise picks the two-address accumulate form and copies the constant into
+// the accumulator before every step of the chain (the latency-bound solo level takes A3; the other
+// kernels keep the compiler's choice, which holds their register count).  Same value either way.
+template <bool A3>
+__device__ __forceinline__ double fma3(double a, double b, double c)
+{
+    if constexpr (A3) {
+        double r;
+        asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+        return r;
+    } else {
+        return fma(a, b, c);
+    }
+}
+
 // cos and sin of a stage offset 0 <= d <= pi/4 (steps never exceed an eighth of the RF
 // period): Maclaurin series through d^16 and d^17; the first omitted terms are below 3e-18.
+template <bool A3 = false>
 __device__ __forceinline__ void small_sincos(double d, double& c, double& s)
 {
     constexpr double f2 = 1.0 / 2, f3 = f2 / 3, f4 = f3 / 4, f5 = f4 / 5, f6 = f5 / 6, f7 = f6 / 7,
@@ -425,22 +442,22 @@ __device__ __forceinline__ void small_sincos(double d, double& c, double& s)
                      f13 = f12 / 13, f14 = f13 / 14, f15 = f14 / 15, f16 = f15 / 16, f17 = f16 / 17;
     const double z = d * d;
     double pc = f16;
-    pc = pc * z - f14;
-    pc = pc * z + f12;
-    pc = pc * z - f10;
-    pc = pc * z + f8;
-    pc = pc * z - f6;
-    pc = pc * z + f4;
-    pc = pc * z - f2;
-    c = pc * z + 1.0;
+    pc = fma3<A3>(pc, z, -f14);
+    pc = fma3<A3>(pc, z, f12);
+    pc = fma3<A3>(pc, z, -f10);
+    pc = fma3<A3>(pc, z, f8);
+    pc = fma3<A3>(pc, z, -f6);
+    pc = fma3<A3>(pc, z, f4);
+    pc = fma3<A3>(pc, z, -f2);
+    c = fma3<A3>(pc, z, 1.0);
     double ps = f17;
-    ps = ps * z - f15;
-    ps = ps * z + f13;
-    ps = ps * z - f11;
-    ps = ps * z + f9;
-    ps = ps * z - f7;
-    ps = ps * z + f5;
-    ps = ps * z - f3;
+    ps = fma3<A3>(ps, z, -f15);
+    ps = fma3<A3>(ps, z, f13);
+    ps = fma3<A3>(ps, z, -f11);
+    ps = fma3<A3>(ps, z, f9);
+    ps = fma3<A3>(ps, z, -f7);
+    ps = fma3<A3>(ps, z, f5);
+    ps = fma3<A3>(ps, z, -f3);
     s = d + d * (ps * z);
 }
 
@@ -1347,6 +1364,7 @@ __device__ __forceinline__ void traj4_store(const Work& W, int64_t i, const Traj
 // ---------------------------------------------------------------------------------------
 struct Traj8 {
     double x, v, F1;   // this lane's coordinate (negated on ion lanes)
+    double m;          // this lane's inverse mass: 1/m_a on atom lanes, 1/m_i on ion lanes
     Scal S;
     Lane L;
 };
@@ -1404,7 +1422,7 @@ __device__ __forceinline__ StageCos stage_cos8(double tau, double phase0, double
     asm volatile("" ::"v"(r));
     const double a = O.l0 ? r : O.cl * h;
     double c, s;
-    small_sincos(a, c, s);
+    small_sincos<true>(a, c, s);
     double sb, cb;
     phase_quadrant(k, quad_bcast<0, true>(c), quad_bcast<0, true>(s), sb, cb);
     const double cs = cos_comb(cb, sb, c, s);
@@ -1433,20 +1451,22 @@ __device__ __forceinline__ Sep8 sep8(double X)
     return D;
 }
 
-// Acceleration of this lane's coordinate at stage position X with separation D, by the expressions of
-// acc_atom and acc_ion.
-__device__ __forceinline__ double accel8(const KParams& P, const Lane& L, const Oct& O, double cs, double X,
-                                         const Sep8& D)
+// Acceleration of this lane's coordinate at stage position X with separation D, with the bits of acc_atom
+// and acc_ion in one expression: with t = s d_k and m = 1/m_a (atom lanes) or 1/m_i (ion lanes),
+//   atom:  (s d_k) / m_a                  = fma(t, m, -0)        (adding -0 leaves every product as is)
+//   ion:   -acc_ion = -fma(-t, m, K X)    = fma(t, m, -(K X))    (X = -x_ion; rounding is sign-symmetric)
+// where K = kA + qc qr and K X is rounded as the product K x_ion of the other forms.
+__device__ __forceinline__ double accel8(const Lane& L, const Oct& O, double m, double cs, double X, const Sep8& D)
 {
     const double s = force_scale_rr(L, D.rr);
     const double qc = L.qx_half * cs;
-    const double aa = acc_atom(L, s, D.dk);
-    const double ai = acc_ion(P.inv_mi, s, D.dk, O.kA, qc, O.qr, -X);
-    return O.atom ? aa : -ai;
+    const double kx = (O.kA + qc * O.qr) * X;
+    const double c = O.atom ? 0.0 : kx;
+    return fma(s * D.dk, m, -c);
 }
-__device__ __forceinline__ double accel8(const KParams& P, const Lane& L, const Oct& O, double cs, double X)
+__device__ __forceinline__ double accel8(const Lane& L, const Oct& O, double m, double cs, double X)
 {
-    return accel8(P, L, O, cs, X, sep8(X));
+    return accel8(L, O, m, cs, X, sep8(X));
 }
 
 // Everything a step of the eight-lane form computes before its bookkeeping: the fifth-order state, the
@@ -1464,11 +1484,11 @@ __device__ __forceinline__ Step8 traj8_trial(const KParams& P, const StepK& K, c
 {
     const double hh = h * h;
     const StageCos C = stage_cos8(T.S.tau, T.L.phase0, h, O);
-    const double F2 = accel8(P, T.L, O, C.c2, stage2(T.x, T.v, h, B));
-    const double F3 = accel8(P, T.L, O, C.c3, stage3(T.x, T.v, h, hh, T.F1, B));
-    const double F4 = accel8(P, T.L, O, C.c4, stage4(T.x, T.v, h, hh, T.F1, F2, B));
-    const double F5 = accel8(P, T.L, O, C.c5, stage5(T.x, T.v, h, hh, T.F1, F2, F3, B));
-    const double F6 = accel8(P, T.L, O, C.c6, stage6(T.x, T.v, h, hh, T.F1, F2, F3, F4, B));
+    const double F2 = accel8(T.L, O, T.m, C.c2, stage2(T.x, T.v, h, B));
+    const double F3 = accel8(T.L, O, T.m, C.c3, stage3(T.x, T.v, h, hh, T.F1, B));
+    const double F4 = accel8(T.L, O, T.m, C.c4, stage4(T.x, T.v, h, hh, T.F1, F2, B));
+    const double F5 = accel8(T.L, O, T.m, C.c5, stage5(T.x, T.v, h, hh, T.F1, F2, F3, B));
+    const double F6 = accel8(T.L, O, T.m, C.c6, stage6(T.x, T.v, h, hh, T.F1, F2, F3, F4, B));
     Step8 R;
     R.x5 = sol_x(T.x, T.v, h, hh, T.F1, F2, F3, F4, F5, B);
     R.v5 = sol_v(T.v, h, T.F1, F3, F4, F5, F6, B);
@@ -1477,7 +1497,7 @@ __device__ __forceinline__ Step8 traj8_trial(const KParams& P, const StepK& K, c
     R.F7 = 0.0;
     R.finite = true;
     if (!SECANT || cond<true>(!exiting)) {
-        R.F7 = accel8(P, T.L, O, C.c6, R.x5, D);
+        R.F7 = accel8(T.L, O, T.m, C.c6, R.x5, D);
         const double rx = err_ratio(err_x(hh, T.F1, F2, F3, F4, F5, F6, B), T.x, R.x5, K.rtol, K.atol);
         const double rv = err_ratio(err_v(h, T.F1, F3, F4, F5, F6, R.F7, B), T.v, R.v5, K.rtol, K.atol);
         // every octet of the wave holds the same trajectory: a wave ballot is the octet's OR
@@ -1527,48 +1547,54 @@ __device__ __forceinline__ void traj8_advance(const KParams& P, const StepK& K, 
     traj8_finish<CE>(K, T, h, fin, R);
 }
 
-// Steps of the eight-lane form, the common case in a loop of its own.  Almost every step is an ordinary
-// one (stepping mode, under the step cap, not the final step, h above its floor) that is accepted with
-// nothing crossed (no periapsis inside r_b, no separation floor, no exit crossing); for it the
-// prologue and epilogue reduce to one uniform test each and the plain update below, which is what
-// step_prologue and step_epilogue do in that case.  The first step that is not such a step goes
-// through the general path and ends the call.  `iters` counts the attempted steps (and stops).
+// Steps of the eight-lane form, the common cases in a loop of their own.  Almost every step is an
+// ordinary one (stepping mode, under the step cap, not the final step, h above its floor) that is either
+// rejected or accepted with nothing crossed (no periapsis inside r_b, no separation floor, no exit
+// crossing, finite state).  For these the prologue and epilogue reduce to one uniform test each and the
+// plain updates below, which are what step_prologue and step_epilogue do in these cases.  At the first
+// step that is not such a step the loop ends with the state as it was before that step, and the general
+// path takes the step again from there (same inputs, same bits); the trial's results never leave the
+// loop, so its state stays in fixed registers.  `iters` counts the attempted steps (and stops).
 template <bool CE>
 __device__ __forceinline__ void traj8_run(const KParams& P, const StepK& K, Traj8& T, const Tab& B, const Oct& O,
                                           uint64_t& iters)
 {
     Scal& S = T.S;
     for (;;) {
-        ++iters;
-        const bool plain = S.mode == 0 && S.nacc < K.max_steps && !(S.h >= K.tau_max - S.tau) && !(S.h < K.hmin);
-        if (!cond<true>(plain)) {
-            traj8_advance<CE>(P, K, T, B, O);
-            return;
-        }
+        const bool plain = (S.mode == 0) & (S.nacc < K.max_steps) & !(S.h >= K.tau_max - S.tau) & !(S.h < K.hmin);
+        if (!cond<true>(plain)) break;
         const double h = S.h;
         const Step8 R = traj8_trial<CE, false>(P, K, T, B, O, h, false);
+        const bool acc = R.en <= 1.0;
         const double ex_prev = CE ? R.e_prev : S.rho_prev, ex_new = CE ? R.e_new : R.rho_new;
+        // bitwise, not short-circuit, so that no condition becomes a branch of its own
         const bool bounce =
-            S.s_prev < 0.0 && R.s_new >= 0.0 && fmin(S.rho_prev, R.rho_new) < T.L.rm2 * K.rb_ratio2;
+            (S.s_prev < 0.0) & (R.s_new >= 0.0) & (fmin(S.rho_prev, R.rho_new) < T.L.rm2 * K.rb_ratio2);
         const bool floor = R.rho_new < 0.01 * T.L.rm2;
-        const bool crossing = ex_prev <= K.r0sq && ex_new > K.r0sq && (CE ? R.se_new : R.s_new) > 0.0;
-        const bool quiet = R.en <= 1.0 && R.finite && !bounce && !floor && !crossing;
-        if (!cond<true>(quiet)) {
-            traj8_finish<CE>(K, T, h, false, R);
-            return;
-        }
+        const bool crossing = (ex_prev <= K.r0sq) & (ex_new > K.r0sq) & ((CE ? R.se_new : R.s_new) > 0.0);
+        const bool event = acc & (!R.finite | bounce | floor | crossing);
+        if (cond<true>(event)) break;
+        ++iters;
         S.nrhs += 6;
-        S.nacc++;
-        S.status |= bound_state(T.L, R.rho_new, R.ww) ? (uint32_t)IAT_ST_BOUND_SEEN : 0u;
-        S.tau = S.tau + h;
-        S.rho_prev = R.rho_new;
-        S.s_prev = R.s_new;
-        S.h = fmin(K.hmax, h * step_factor(R.en, S.last_rej != 0));
-        S.last_rej = 0;
-        T.x = R.x5;
-        T.v = R.v5;
-        T.F1 = R.F7;
+        if (cond<true>(acc)) {
+            S.nacc++;
+            S.status |= bound_state(T.L, R.rho_new, R.ww) ? (uint32_t)IAT_ST_BOUND_SEEN : 0u;
+            S.tau = S.tau + h;
+            S.rho_prev = R.rho_new;
+            S.s_prev = R.s_new;
+            S.h = fmin(K.hmax, h * step_factor(R.en, S.last_rej != 0));
+            S.last_rej = 0;
+            T.x = R.x5;
+            T.v = R.v5;
+            T.F1 = R.F7;
+        } else {
+            S.nrej++;
+            S.h = h * reject_factor(R.en);
+            S.last_rej = 1;
+        }
     }
+    ++iters;
+    traj8_advance<CE>(P, K, T, B, O);
 }
 
 // A record of the continuation layout (cont_save) into the eight-lane form.

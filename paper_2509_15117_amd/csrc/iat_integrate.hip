@@ -317,6 +317,7 @@ __global__ void __launch_bounds__(256) k_integrate_solo(KParams P, Work W, Cont 
         Traj8 T;
         int64_t i;
         cont_load8(W, C, (int64_t)slot, atom, ax, T, i);
+        T.m = atom ? T.L.inv_ma : P.inv_mi;
         const int32_t resumed_at = T.S.nacc + T.S.nrej, resumed_rhs = T.S.nrhs;
         while (!__builtin_amdgcn_readfirstlane(T.S.done)) traj8_run<CE>(P, K, T, B, O, iters);
         if (lane < 8) traj8_store(W, i, T, l);
