@@ -60,11 +60,53 @@ def test_roofline_names_the_dominant_kernel_of_the_three(name):
     assert r["kernel"] == dom["kernel"] and r["achieved"] == dom["achieved"] and r["traffic"] == dom["traffic"]
 
 
-def test_headline_record_carries_the_solo_phase_and_current_traffic():
+def test_grid_record_carries_the_solo_phase_and_its_traffic():
     d = json.load(open(os.path.join(ROOT, "profiles", "bench_yb_rb_grid1024.json")))
     assert set(d["phases_ms"]) == {"setup", "main", "tail", "solo", "observe"}
     assert 0 < d["solo_trajectories"] < d["tail_trajectories"] < d["config"]["trajectories"]
-    # the headline line was taken while the PMC counters matched its kernel sources
+    # that line was taken while the PMC counters matched its kernel sources
     assert isinstance(d["roofline"]["traffic"], int) and d["roofline"]["traffic"] > 0
     cp = d["critical_path"]
     assert abs(cp["tail_ms"] - d["phases_ms"]["tail"] - d["phases_ms"]["solo"]) < 1e-6 * cp["tail_ms"]
+
+
+@pytest.mark.parametrize("name", ["bench_stream_li_k_cs_1e8.json", "bench_stream_li_k_cs_1e8_profiled.json"])
+def test_stream_headline_record(name):
+    """The default line: the 1e8 Li/K/Cs stream, one step = one 2^22-id chunk, the timed chunks integrated
+    as one batch; refill against plain on a matched chunk; the critical path of the batch's tail."""
+    d = json.load(open(os.path.join(ROOT, "profiles", name)))
+    c = d["config"]
+    assert c["workload"] == "stream_li_k_cs_1e8" and c["trajectories_in_stream"] == 100_000_000
+    assert c["chunk"] == 1 << 22 and d["steps"] == 20
+    lo, hi = c["timed_ids"]
+    assert hi - lo == d["steps"] * c["chunk"]
+    assert abs(d["value"] - (hi - lo) / (d["ms_per_step"] * d["steps"] * 1e-3)) < 1e-6 * d["value"]
+    assert set(c["launch"]) == {"block", "refill_every", "blocks_per_cu", "step_budget"}
+    ph = d["phases_ms"]
+    assert set(ph) == {"setup", "main", "tail", "solo", "observe"}
+    assert sum(ph.values()) <= d["ms_per_step"] * d["steps"] * 1.001
+    assert 0 < d["solo_trajectories"] < d["tail_trajectories"] < hi - lo
+    cp = d["critical_path"]
+    assert abs(cp["tail_ms"] - ph["tail"] - ph["solo"]) < 1e-6 * cp["tail_ms"]
+    assert 0.5 < cp["frac_of_tail"] <= 1.0
+    assert cp["trajectory_id"] == d["longest_trajectory"]["id"] and lo <= cp["trajectory_id"] < hi
+    # refill against plain on the same chunk
+    assert d["plain"]["sample"].startswith("one chunk") and d["speedup_vs_plain"] > 1.0
+    assert set(d["p_complex_by_species"]) == {"Li6", "K40", "Cs133"}
+
+
+def test_stream_trace_agrees_with_its_line():
+    """profiles/k_integrate__stream_li_k_cs_1e8.md lists the timed batch's three dispatches from the
+    kernel trace; each equals the phase the profiled bench line timed with HIP events."""
+    import re
+    d = json.load(open(os.path.join(ROOT, "profiles", "bench_stream_li_k_cs_1e8_profiled.json")))
+    md = open(os.path.join(ROOT, "profiles", "k_integrate__stream_li_k_cs_1e8.md")).read()
+    got = {}
+    for m in re.finditer(r"\| \d+ \| `k_integrate_(persistent|tail|solo)<false>`[^|]*\| ([\d,.]+) \|", md):
+        got[m.group(1)] = float(m.group(2).replace(",", ""))
+    assert set(got) == {"persistent", "tail", "solo"}
+    ph = d["phases_ms"]
+    for k, phase in (("persistent", "main"), ("tail", "tail"), ("solo", "solo")):
+        assert abs(got[k] - ph[phase]) < 0.1, (k, got[k], ph[phase])
+    assert d["roofline"]["kernel"] == "k_integrate_solo"
+    assert abs(d["roofline"]["avg_launch_ms"] - got["solo"]) < 0.1
