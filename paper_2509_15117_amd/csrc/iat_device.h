@@ -1002,20 +1002,16 @@ __device__ __forceinline__ int quad_or(int v)
 // Stage cosines for the four-lane form: the values of stage_cos, with its six polynomial
 // evaluations (the phase remainder and the five stage offsets) shared out over the quad's lanes
 // in two rounds and gathered with quad moves.
+
 template <bool ROW = false>
-__device__ __forceinline__ StageCos stage_cos4(double tau, double phase0, double h, const Tab& T = kTab)
+__device__ __forceinline__ StageCos stage_cos4q(double tau, double phase0, double h, bool l0, double cl, double cl2)
 {
-    const int l = __lane_id() & 3;
-    // per-lane offset coefficients, so each argument is one product: a1 = c_l h (lanes 1..3, lane 0
-    // takes the phase remainder), a2 = c5 h (lanes 0, 2) or 1.0 h = h (lanes 1, 3)
-    const double cl = l == 1 ? T.c2 : (l == 2 ? T.c3 : T.c4);
-    const double cl2 = (l & 1) ? 1.0 : T.c5;
     double k;
     const double r = phase_reduce(tau + phase0, k);
     // every lane reduces the phase: without this the compiler moves the reduction into a branch taken
     // by lane 0 alone, and a quad then runs the lane cases one after another
     asm volatile("" ::"v"(r));
-    const double a1 = l == 0 ? r : cl * h;
+    const double a1 = l0 ? r : cl * h;
     const double a2 = cl2 * h;
     double cA, sA, cB, sB;
     small_sincos(a1, cA, sA);
@@ -1031,26 +1027,67 @@ __device__ __forceinline__ StageCos stage_cos4(double tau, double phase0, double
     return C;
 }
 
+template <bool ROW = false>
+__device__ __forceinline__ StageCos stage_cos4(double tau, double phase0, double h, const Tab& T = kTab)
+{
+    // per-lane offset coefficients, so each argument is one product: a1 = c_l h (lanes 1..3, lane 0
+    // takes the phase remainder), a2 = c5 h (lanes 0, 2) or 1.0 h = h (lanes 1, 3)
+    const int l = __lane_id() & 3;
+    const double cl = l == 1 ? T.c2 : (l == 2 ? T.c3 : T.c4);
+    const double cl2 = (l & 1) ? 1.0 : T.c5;
+    return stage_cos4q<ROW>(tau, phase0, h, l == 0, cl, cl2);
+}
+
 struct Traj4 {
     double xa, xi, va, vi, F1a, F1i;   // this lane's axis
     Scal S;
     Lane L;
 };
 
+// Per-lane constants of the four-lane form.  A kernel that steps many times computes them once and
+// holds them in registers (quad_consts<true>); evaluated at each use, the compiler may turn their
+// lane-dependent selects into a table in private memory.
+struct Quad4 {
+    int k;            // this lane's axis (lane 3 shadows axis 2)
+    bool l0;          // lane 0: evaluates the series of the phase remainder
+    double kA, qr;    // a_k / 4 and q_k / q_x of the axis
+    double cl, cl2;   // stage-cosine offsets of the lane's two series: c2, c3, c4 (lanes 1..3) and c5 or 1
+};
+template <bool PIN>
+__device__ __forceinline__ Quad4 quad_consts(const KParams& P, const Tab& T)
+{
+    const int l = __lane_id() & 3;
+    Quad4 Q;
+    Q.k = min(l, 2);
+    Q.l0 = l == 0;
+    Q.kA = Q.k == 0 ? P.kA[0] : (Q.k == 1 ? P.kA[1] : P.kA[2]);
+    Q.qr = Q.k == 0 ? P.q_ratio[0] : (Q.k == 1 ? P.q_ratio[1] : P.q_ratio[2]);
+    Q.cl = l == 1 ? T.c2 : (l == 2 ? T.c3 : T.c4);
+    Q.cl2 = (l & 1) ? 1.0 : T.c5;
+    if (PIN) asm volatile("" : "+v"(Q.kA), "+v"(Q.qr), "+v"(Q.cl), "+v"(Q.cl2));
+    return Q;
+}
+
 __device__ __forceinline__ int quad_axis() { return min((int)(__lane_id() & 3), 2); }
 
 template <bool ROW = false>
-__device__ __forceinline__ void accel4(const KParams& P, const Lane& L, int k, double cs, double Xa, double Xi,
-                                       double& Aa, double& Ai)
+__device__ __forceinline__ void accel4q(const KParams& P, const Lane& L, double kA, double qr, double cs, double Xa,
+                                        double Xi, double& Aa, double& Ai)
 {
     const double dk = Xa - Xi;
     const double d0 = quad_bcast<0, ROW>(dk), d1 = quad_bcast<1, ROW>(dk), d2 = quad_bcast<2, ROW>(dk);
     const double s = force_scale(L, d0, d1, d2);
     const double qc = L.qx_half * cs;
-    const double kA = k == 0 ? P.kA[0] : (k == 1 ? P.kA[1] : P.kA[2]);
-    const double qr = k == 0 ? P.q_ratio[0] : (k == 1 ? P.q_ratio[1] : P.q_ratio[2]);
     Aa = acc_atom(L, s, dk);
     Ai = acc_ion(P.inv_mi, s, dk, kA, qc, qr, Xi);
+}
+template <bool ROW = false>
+__device__ __forceinline__ void accel4(const KParams& P, const Lane& L, int k, double cs, double Xa, double Xi,
+                                       double& Aa, double& Ai)
+{
+    const double kA = k == 0 ? P.kA[0] : (k == 1 ? P.kA[1] : P.kA[2]);
+    const double qr = k == 0 ? P.q_ratio[0] : (k == 1 ? P.q_ratio[1] : P.q_ratio[2]);
+    accel4q<ROW>(P, L, kA, qr, cs, Xa, Xi, Aa, Ai);
 }
 
 // Start of a four-lane trajectory from the work buffer (same bits as traj1_start).
@@ -1082,6 +1119,86 @@ __device__ inline void traj4_start(const KParams& P, const Work& W, int64_t i, T
     T.S.s_prev = dot3(d0, d1, d2, w0, w1, w2);
 }
 
+// Everything a step of the four-lane form computes before its bookkeeping (the four-lane counterpart of
+// Step8): this lane's axis of the fifth-order state and of the FSAL acceleration, the error norm and the
+// geometry of the new state.
+struct Step4 {
+    double x5a, x5i, v5a, v5i, F7a, F7i, en;
+    bool finite;
+    double rho_new, s_new, ww, e_prev, e_new, se_new;
+};
+template <bool CE, bool ROW>
+__device__ __forceinline__ Step4 traj4_trial(const KParams& P, const StepK& K, const Traj4& T, const Tab& B,
+                                             const Quad4& Q, double h, bool exiting)
+{
+    const double hh = h * h;
+    const StageCos C = stage_cos4q<ROW>(T.S.tau, T.L.phase0, h, Q.l0, Q.cl, Q.cl2);
+    double F2a, F2i, F3a, F3i, F4a, F4i, F5a, F5i, F6a, F6i;
+    accel4q<ROW>(P, T.L, Q.kA, Q.qr, C.c2, stage2(T.xa, T.va, h, B), stage2(T.xi, T.vi, h, B), F2a, F2i);
+    accel4q<ROW>(P, T.L, Q.kA, Q.qr, C.c3, stage3(T.xa, T.va, h, hh, T.F1a, B), stage3(T.xi, T.vi, h, hh, T.F1i, B), F3a, F3i);
+    accel4q<ROW>(P, T.L, Q.kA, Q.qr, C.c4, stage4(T.xa, T.va, h, hh, T.F1a, F2a, B), stage4(T.xi, T.vi, h, hh, T.F1i, F2i, B), F4a,
+           F4i);
+    accel4q<ROW>(P, T.L, Q.kA, Q.qr, C.c5, stage5(T.xa, T.va, h, hh, T.F1a, F2a, F3a, B),
+           stage5(T.xi, T.vi, h, hh, T.F1i, F2i, F3i, B), F5a, F5i);
+    accel4q<ROW>(P, T.L, Q.kA, Q.qr, C.c6, stage6(T.xa, T.va, h, hh, T.F1a, F2a, F3a, F4a, B),
+           stage6(T.xi, T.vi, h, hh, T.F1i, F2i, F3i, F4i, B), F6a, F6i);
+    Step4 R;
+    R.x5a = sol_x(T.xa, T.va, h, hh, T.F1a, F2a, F3a, F4a, F5a, B);
+    R.x5i = sol_x(T.xi, T.vi, h, hh, T.F1i, F2i, F3i, F4i, F5i, B);
+    R.v5a = sol_v(T.va, h, T.F1a, F3a, F4a, F5a, F6a, B);
+    R.v5i = sol_v(T.vi, h, T.F1i, F3i, F4i, F5i, F6i, B);
+    R.en = 0.0;
+    R.F7a = R.F7i = 0.0;
+    R.finite = true;
+    if (!exiting) {
+        accel4q<ROW>(P, T.L, Q.kA, Q.qr, C.c6, R.x5a, R.x5i, R.F7a, R.F7i);
+        const double ra = err_ratio(err_x(hh, T.F1a, F2a, F3a, F4a, F5a, F6a, B), T.xa, R.x5a, K.rtol, K.atol);
+        const double ri = err_ratio(err_x(hh, T.F1i, F2i, F3i, F4i, F5i, F6i, B), T.xi, R.x5i, K.rtol, K.atol);
+        const double rva = err_ratio(err_v(h, T.F1a, F3a, F4a, F5a, F6a, R.F7a, B), T.va, R.v5a, K.rtol, K.atol);
+        const double rvi = err_ratio(err_v(h, T.F1i, F3i, F4i, F5i, F6i, R.F7i, B), T.vi, R.v5i, K.rtol, K.atol);
+        const int bad = quad_or((ratio_bad(ra) || ratio_bad(ri) || ratio_bad(rva) || ratio_bad(rvi)) ? 1 : 0);
+        const int nonfin =
+            quad_or((is_finite(R.x5a) && is_finite(R.x5i) && is_finite(R.v5a) && is_finite(R.v5i)) ? 0 : 1);
+        const double m = quad_max(fmax(fmax(ra, rva), fmax(ri, rvi)));
+        R.en = bad ? __builtin_nan("") : m;
+        R.finite = nonfin == 0;
+    }
+    const double dk = R.x5a - R.x5i, wk = R.v5a - R.v5i;
+    const double d0 = quad_bcast<0, ROW>(dk), d1 = quad_bcast<1, ROW>(dk), d2 = quad_bcast<2, ROW>(dk);
+    const double w0 = quad_bcast<0, ROW>(wk), w1 = quad_bcast<1, ROW>(wk), w2 = quad_bcast<2, ROW>(wk);
+    R.rho_new = dot3(d0, d1, d2, d0, d1, d2);
+    R.s_new = dot3(d0, d1, d2, w0, w1, w2);
+    R.ww = dot3(w0, w1, w2, w0, w1, w2);
+    R.e_prev = R.e_new = R.se_new = 0.0;
+    if (CE) {
+        const double p0 = quad_bcast<0, ROW>(T.xa), p1 = quad_bcast<1, ROW>(T.xa), p2 = quad_bcast<2, ROW>(T.xa);
+        const double a0 = quad_bcast<0, ROW>(R.x5a), a1 = quad_bcast<1, ROW>(R.x5a), a2 = quad_bcast<2, ROW>(R.x5a);
+        const double u0 = quad_bcast<0, ROW>(R.v5a), u1 = quad_bcast<1, ROW>(R.v5a), u2 = quad_bcast<2, ROW>(R.v5a);
+        R.e_prev = dot3(p0, p1, p2, p0, p1, p2);
+        R.e_new = dot3(a0, a1, a2, a0, a1, a2);
+        R.se_new = dot3(a0, a1, a2, u0, u1, u2);
+    }
+    return R;
+}
+
+// Bookkeeping of the four-lane form: the shared epilogue and the state update it decides.
+template <bool CE>
+__device__ __forceinline__ StepOutcome traj4_finish(const StepK& K, Traj4& T, double h, bool fin, const Step4& R)
+{
+    const StepOutcome o = step_epilogue<CE>(K, T.S, T.L, h, fin, R.en, R.finite, R.rho_new, R.s_new, R.ww, R.e_prev,
+                                            R.e_new, R.se_new);
+    // selects, not branches: with branches the compiler keeps R in private memory
+    const bool fsal = o == OUT_ACCEPT || o == OUT_TMAX;
+    const bool moved = fsal || o == OUT_SECANT_DONE || o == OUT_STOP_RFLOOR;
+    T.xa = moved ? R.x5a : T.xa;
+    T.xi = moved ? R.x5i : T.xi;
+    T.va = moved ? R.v5a : T.va;
+    T.vi = moved ? R.v5i : T.vi;
+    T.F1a = fsal ? R.F7a : T.F1a;
+    T.F1i = fsal ? R.F7i : T.F1i;
+    return o;
+}
+
 // One attempted step of the four-lane form.  Returns the StepOutcome, or -1 when the trajectory
 // stopped before stepping (step cap, step underflow); h_used receives the step size tried.
 template <bool CE = false, bool ROW = false>
@@ -1093,69 +1210,10 @@ __device__ __forceinline__ int traj4_step_k(const KParams& P, const StepK& K, Tr
     h_used = 0.0;
     if (!step_prologue(K, T.S, h, fin)) return -1;
     h_used = h;
-    const bool exiting = T.S.mode != 0;
-    const int k = quad_axis();
-    const double hh = h * h;
-    const StageCos C = stage_cos4<ROW>(T.S.tau, T.L.phase0, h, B);
-    double F2a, F2i, F3a, F3i, F4a, F4i, F5a, F5i, F6a, F6i;
-    accel4<ROW>(P, T.L, k, C.c2, stage2(T.xa, T.va, h, B), stage2(T.xi, T.vi, h, B), F2a, F2i);
-    accel4<ROW>(P, T.L, k, C.c3, stage3(T.xa, T.va, h, hh, T.F1a, B), stage3(T.xi, T.vi, h, hh, T.F1i, B), F3a, F3i);
-    accel4<ROW>(P, T.L, k, C.c4, stage4(T.xa, T.va, h, hh, T.F1a, F2a, B), stage4(T.xi, T.vi, h, hh, T.F1i, F2i, B), F4a,
-           F4i);
-    accel4<ROW>(P, T.L, k, C.c5, stage5(T.xa, T.va, h, hh, T.F1a, F2a, F3a, B),
-           stage5(T.xi, T.vi, h, hh, T.F1i, F2i, F3i, B), F5a, F5i);
-    accel4<ROW>(P, T.L, k, C.c6, stage6(T.xa, T.va, h, hh, T.F1a, F2a, F3a, F4a, B),
-           stage6(T.xi, T.vi, h, hh, T.F1i, F2i, F3i, F4i, B), F6a, F6i);
-    const double x5a = sol_x(T.xa, T.va, h, hh, T.F1a, F2a, F3a, F4a, F5a, B);
-    const double x5i = sol_x(T.xi, T.vi, h, hh, T.F1i, F2i, F3i, F4i, F5i, B);
-    const double v5a = sol_v(T.va, h, T.F1a, F3a, F4a, F5a, F6a, B);
-    const double v5i = sol_v(T.vi, h, T.F1i, F3i, F4i, F5i, F6i, B);
-    double en = 0.0, F7a = 0.0, F7i = 0.0;
-    bool finite = true;
-    if (!exiting) {
-        accel4<ROW>(P, T.L, k, C.c6, x5a, x5i, F7a, F7i);
-        const double ra = err_ratio(err_x(hh, T.F1a, F2a, F3a, F4a, F5a, F6a, B), T.xa, x5a, K.rtol, K.atol);
-        const double ri = err_ratio(err_x(hh, T.F1i, F2i, F3i, F4i, F5i, F6i, B), T.xi, x5i, K.rtol, K.atol);
-        const double rva = err_ratio(err_v(h, T.F1a, F3a, F4a, F5a, F6a, F7a, B), T.va, v5a, K.rtol, K.atol);
-        const double rvi = err_ratio(err_v(h, T.F1i, F3i, F4i, F5i, F6i, F7i, B), T.vi, v5i, K.rtol, K.atol);
-        const int bad = quad_or((ratio_bad(ra) || ratio_bad(ri) || ratio_bad(rva) || ratio_bad(rvi)) ? 1 : 0);
-        const int nonfin =
-            quad_or((is_finite(x5a) && is_finite(x5i) && is_finite(v5a) && is_finite(v5i)) ? 0 : 1);
-        const double m = quad_max(fmax(fmax(ra, rva), fmax(ri, rvi)));
-        en = bad ? __builtin_nan("") : m;
-        finite = nonfin == 0;
-    }
-    const double dk = x5a - x5i, wk = v5a - v5i;
-    const double d0 = quad_bcast<0, ROW>(dk), d1 = quad_bcast<1, ROW>(dk), d2 = quad_bcast<2, ROW>(dk);
-    const double w0 = quad_bcast<0, ROW>(wk), w1 = quad_bcast<1, ROW>(wk), w2 = quad_bcast<2, ROW>(wk);
-    const double rho_new = dot3(d0, d1, d2, d0, d1, d2);
-    const double s_new = dot3(d0, d1, d2, w0, w1, w2);
-    const double ww = dot3(w0, w1, w2, w0, w1, w2);
-    double e_prev = 0.0, e_new = 0.0, se_new = 0.0;
-    if (CE) {
-        const double p0 = quad_bcast<0, ROW>(T.xa), p1 = quad_bcast<1, ROW>(T.xa), p2 = quad_bcast<2, ROW>(T.xa);
-        const double a0 = quad_bcast<0, ROW>(x5a), a1 = quad_bcast<1, ROW>(x5a), a2 = quad_bcast<2, ROW>(x5a);
-        const double u0 = quad_bcast<0, ROW>(v5a), u1 = quad_bcast<1, ROW>(v5a), u2 = quad_bcast<2, ROW>(v5a);
-        e_prev = dot3(p0, p1, p2, p0, p1, p2);
-        e_new = dot3(a0, a1, a2, a0, a1, a2);
-        se_new = dot3(a0, a1, a2, u0, u1, u2);
-    }
-    const StepOutcome o = step_epilogue<CE>(K, T.S, T.L, h, fin, en, finite, rho_new, s_new, ww, e_prev, e_new, se_new);
-    if (o == OUT_SECANT_DONE || o == OUT_STOP_RFLOOR) {
-        T.xa = x5a;
-        T.xi = x5i;
-        T.va = v5a;
-        T.vi = v5i;
-    } else if (o == OUT_ACCEPT || o == OUT_TMAX) {
-        T.xa = x5a;
-        T.xi = x5i;
-        T.va = v5a;
-        T.vi = v5i;
-        T.F1a = F7a;
-        T.F1i = F7i;
-    }
-    return (int)o;
+    const Step4 R = traj4_trial<CE, ROW>(P, K, T, B, quad_consts<false>(P, B), h, T.S.mode != 0);
+    return (int)traj4_finish<CE>(K, T, h, fin, R);
 }
+
 template <bool CE = false>
 __device__ __forceinline__ int traj4_step(const KParams& P, Traj4& T, double& h_used, const Tab& B = kTab)
 {
@@ -1173,6 +1231,61 @@ __device__ __forceinline__ void traj4_advance_k(const KParams& P, const StepK& K
 {
     double h;
     (void)traj4_step_k<CE, ROW>(P, K, T, h, B);
+}
+
+// One step of the four-lane form for the lanes that call it (every quad of them a running trajectory),
+// the common cases first.  When every calling quad is on an ordinary step (stepping mode, under the step
+// cap, not the final step, h above its floor) and none of them, once the step is tried, is accepted with
+// an event (periapsis inside r_b, separation floor, exit crossing, non-finite state), each quad is either
+// accepted or rejected with the plain updates of step_epilogue for those cases, chosen per lane without a
+// branch.  Otherwise every calling quad takes the general path (the same step, the same bits).
+template <bool CE = false>
+__device__ __forceinline__ void traj4_step_fast(const KParams& P, const StepK& K, Traj4& T, const Tab& B,
+                                                const Quad4& Q)
+{
+    Scal& S = T.S;
+    const bool plain = (S.mode == 0) & (S.nacc < K.max_steps) & !(S.h >= K.tau_max - S.tau) & !(S.h < K.hmin);
+    bool general = __builtin_amdgcn_ballot_w64(!plain) != 0;
+    double h = S.h;
+    bool fin = false;
+    if (general && !step_prologue(K, S, h, fin)) return;
+    const Step4 R = traj4_trial<CE, false>(P, K, T, B, Q, h, S.mode != 0);
+    const bool acc = R.en <= 1.0;
+    if (!general) {
+        const double ex_prev = CE ? R.e_prev : S.rho_prev, ex_new = CE ? R.e_new : R.rho_new;
+        const bool bounce =
+            (S.s_prev < 0.0) & (R.s_new >= 0.0) & (fmin(S.rho_prev, R.rho_new) < T.L.rm2 * K.rb_ratio2);
+        const bool floor = R.rho_new < 0.01 * T.L.rm2;
+        const bool crossing = (ex_prev <= K.r0sq) & (ex_new > K.r0sq) & ((CE ? R.se_new : R.s_new) > 0.0);
+        general = __builtin_amdgcn_ballot_w64(acc & (!R.finite | bounce | floor | crossing)) != 0;
+    }
+    if (general) {
+        (void)traj4_finish<CE>(K, T, h, fin, R);
+        return;
+    }
+    S.nrhs += 6;
+    // both step factors before the branch, so that they share the one root of en
+    const double h_acc = fmin(K.hmax, h * step_factor(R.en, S.last_rej != 0));
+    const double h_rej = h * reject_factor(R.en);
+    if (acc) {
+        S.nacc++;
+        S.status |= bound_state(T.L, R.rho_new, R.ww) ? (uint32_t)IAT_ST_BOUND_SEEN : 0u;
+        S.tau = S.tau + h;
+        S.rho_prev = R.rho_new;
+        S.s_prev = R.s_new;
+        S.h = h_acc;
+        S.last_rej = 0;
+        T.xa = R.x5a;
+        T.xi = R.x5i;
+        T.va = R.v5a;
+        T.vi = R.v5i;
+        T.F1a = R.F7a;
+        T.F1i = R.F7i;
+    } else {
+        S.nrej++;
+        S.h = h_rej;
+        S.last_rej = 1;
+    }
 }
 
 // ---------------------------------------------------------------------------------------

@@ -202,6 +202,7 @@ __device__ __forceinline__ void tail_run(const KParams& P, const Work& W, const 
     bool few_left = false;       // pop_limit rule: the remaining population fits the solo level
     const Tab B = tab_in_registers();
     const StepK K = step_k_in_registers(P);
+    const Quad4 Q = quad_consts<true>(P, B);
     for (;;) {
         const uint64_t mask = __ballot(need && leader);
         if (mask) {
@@ -224,7 +225,12 @@ __device__ __forceinline__ void tail_run(const KParams& P, const Work& W, const 
         // every lane reads the counter in the same load, so the flag is wave-uniform
         if (pop_limit > 0 && may_suspend && !few_left && (iters & 63) == 0)
             few_left = total - (int64_t)__hip_atomic_load(gone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= pop_limit;
-        if (active && !T.S.done) traj4_advance_k<CE, QUADS == 1>(P, K, T, B);
+        if (active && !T.S.done) {
+            if constexpr (QUADS == 1)
+                traj4_advance_k<CE, true>(P, K, T, B);
+            else
+                traj4_step_fast<CE>(P, K, T, B, Q);
+        }
         ++iters;
         if (active && T.S.done) {
             traj4_store(W, i, T, lane & 3);
