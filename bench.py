@@ -289,8 +289,9 @@ def main_stream(args):
         batch(m, 0, wo, None)
         del wo
     if not args.no_autotune:
-        # the main kernel's launch shape, timed on ids of the warm-up range (outside the timed batch)
-        launch = api.autotune(w, n=min(1 << 20, max(id0, 1 << 16)), id0=0, cache=args.autotune or None)
+        # the main kernel's launch shape, timed on the warm-up range (outside the timed batch): a whole
+        # chunk, so that the end of each trial launch is a small part of it, as in the batch
+        launch = api.autotune(w, n=min(C, max(id0, 1 << 16)), id0=0, cache=args.autotune or None)
         print(f"[bench] autotuned launch {launch}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     hist = torch.zeros(len(w.gen.species) * 2 * 64 + 256, dtype=torch.float64, device=dev)
