@@ -554,14 +554,20 @@ def sources_digest():
 
 def traffic_bytes(path, workload_name, kernel):
     """HBM bytes per launch of `kernel` from PMC runs (FETCH_SIZE + WRITE_SIZE, scaled by a copy-kernel
-    calibration), or None when absent or taken on other sources."""
+    calibration), or None when absent or taken on other sources.  The file holds one entry per workload
+    under "workloads" (or, in the older layout, one workload at the top level)."""
     try:
         tr = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if tr.get("workload") != workload_name or tr.get("sources") != sources_digest():
+    if tr.get("sources") != sources_digest():
         return None
-    return tr.get("kernels", {}).get(kernel, {}).get("bytes_per_launch")
+    entry = tr.get("workloads", {}).get(workload_name)
+    if entry is None and tr.get("workload") == workload_name:
+        entry = tr
+    if entry is None:
+        return None
+    return entry.get("kernels", {}).get(kernel, {}).get("bytes_per_launch")
 
 
 def calibrate_copy(nbytes, reps):

@@ -34,14 +34,21 @@ def test_traffic_is_reported_only_for_the_sources_it_was_taken_on(tmp_path):
     tr["sources"] = bench.sources_digest()
     p = tmp_path / "t.json"
     p.write_text(json.dumps(tr))
-    wl = tr["workload"]
-    b = bench.traffic_bytes(str(p), wl, "k_integrate_tail")
-    assert b == tr["kernels"]["k_integrate_tail"]["bytes_per_launch"]
+    assert tr["workloads"], "no workload in the traffic record"
+    for wl, entry in tr["workloads"].items():
+        for k, rec in entry["kernels"].items():
+            assert bench.traffic_bytes(str(p), wl, k) == rec["bytes_per_launch"]
+        assert bench.traffic_bytes(str(p), wl, "no_such_kernel") is None
     assert bench.traffic_bytes(str(p), "another_workload", "k_integrate_tail") is None
+    wl = next(iter(tr["workloads"]))
     tr["sources"] = "0" * 64
     p.write_text(json.dumps(tr))
     assert bench.traffic_bytes(str(p), wl, "k_integrate_tail") is None
     assert bench.traffic_bytes(str(tmp_path / "missing.json"), wl, "k_integrate_tail") is None
+    # the older one-workload layout is still read
+    old = {"workload": "w", "sources": bench.sources_digest(), "kernels": {"k": {"bytes_per_launch": 7}}}
+    p.write_text(json.dumps(old))
+    assert bench.traffic_bytes(str(p), "w", "k") == 7
 
 
 @pytest.mark.parametrize("name", RECORDS)
