@@ -49,9 +49,9 @@ def parse():
                     help="cache file of the launch-shape autotuner (stream: it always runs, on the warm-up "
                          "ids; other workloads: only with this option)")
     ap.add_argument("--no-autotune", action="store_true", help="stream: keep the default launch shape")
-    ap.add_argument("--no-graph", action="store_true",
-                    help="chunked workloads: launch every chunk eagerly instead of replaying one captured HIP "
-                         "graph per stream")
+    ap.add_argument("--graph", action="store_true",
+                    help="chunked workloads (not thermal): replay one captured HIP graph per stream for the "
+                         "later chunks instead of launching every chunk eagerly")
     ap.add_argument("--chunk", type=int, default=0, help="ids per chunk (default: the job split evenly over the streams)")
     ap.add_argument("--streams", type=int, default=2, help="streams the chunks are spread over")
     ap.add_argument("--n", type=int, default=0, help="run only the first N ids of the workload")
@@ -161,7 +161,7 @@ def chunked_job(api, torch, w, n, args, stats, kernel):
         print(f"[bench] {kernel}: chunk {c + 1}/{nc} done at {time.perf_counter() - t0:.1f} s", file=sys.stderr,
               flush=True)
 
-    res = api.run_chunks(w, n=n, chunk=chunk, n_streams=args.streams, kernel=kernel, graph=not args.no_graph,
+    res = api.run_chunks(w, n=n, chunk=chunk, n_streams=args.streams, kernel=kernel, graph=args.graph,
                          cells=args.workload in ("sweep", "thermal"),
                          hist=args.workload in ("stream", "stream-chunks", "fig4"), stats=stats,
                          progress=progress)

@@ -381,12 +381,17 @@ def run_chunks(w, *, n: Optional[int] = None, chunk: int = 1 << 22, n_streams: i
     with the chunk's first id read from a device scalar (iat_batch.id0_dev), and replays it for every
     later full chunk after writing that id; the first chunk runs eagerly (code objects, pools) and so
     does a shorter last chunk.  The bits are those of the eager calls (not with sample)."""
+    want = sample is not None
+    if graph and want:
+        raise ValueError("run_chunks: graph replay does not copy out samples")
+    if graph and w.gen.kind == "thermal":
+        # the one large run that replayed thermal chunks from a graph faulted the GPU, cause not found
+        raise ValueError("run_chunks: graph replay is not available for thermal batches")
     n = w.n if n is None else n
     dev = torch.device("cuda", torch.cuda.current_device())
     cur = torch.cuda.current_stream()
     streams = [torch.cuda.Stream(device=dev) for _ in range(max(1, n_streams))]
     m = min(chunk, n)
-    want = sample is not None
     bufs = [alloc_obs(m, dev, counters=want, y_final=want) for _ in streams]
     if want:
         ids_h = torch.as_tensor(sample, dtype=torch.int64).cpu()
@@ -403,8 +408,6 @@ def run_chunks(w, *, n: Optional[int] = None, chunk: int = 1 << 22, n_streams: i
                for _ in streams] if hist_bound else None)
     for s in streams:
         s.wait_stream(cur)
-    if graph and want:
-        raise ValueError("run_chunks: graph replay does not copy out samples")
     offs = [torch.zeros(1, dtype=torch.int64, device=dev) for _ in streams] if graph else None
     graphs = [None] * len(streams)
 

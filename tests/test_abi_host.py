@@ -202,3 +202,12 @@ def test_boxcount_refuses_a_device_id_offset_without_gpu():
     rc = L.iat_reduce(ctypes.byref(api.system_struct(w.system)), api.species_array(w.species()), 1, ctypes.byref(b),
                       ctypes.byref(_obs_dummy()), _abi.REDUCE_BOXCOUNT, ctypes.c_void_p(0x1000), None)
     assert rc == _abi.IAT_EINVAL and "BOXCOUNT" in L.iat_last_error().decode()
+
+
+def test_run_chunks_refuses_graph_replay_of_thermal_batches_without_gpu():
+    """Graph replay of chunks is switched off for thermal batches (refused before any device call)."""
+    from paper_2509_15117_amd import api
+    with pytest.raises(ValueError, match="thermal"):
+        api.run_chunks(W.fig3_thermal(), n=64, chunk=32, graph=True, cells=True)
+    with pytest.raises(ValueError, match="samples"):
+        api.run_chunks(W.config3(), n=64, chunk=32, graph=True, sample=[1, 2])
