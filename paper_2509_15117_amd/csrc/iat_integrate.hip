@@ -24,6 +24,7 @@ namespace iat {
 constexpr int64_t kDefaultBudget = 20000;        // attempted steps before a trajectory moves to 4 lanes
 constexpr int64_t kMaxSuspended = 1 << 23;       // continuation records per call (248 B each)
 constexpr int64_t kMaxSolo = 1 << 16;            // records of the solo level per call
+constexpr int kTailSteps = 4;                    // steps per turn of the four-lane tail kernel's loop (a power of 2)
 
 __device__ __forceinline__ uint64_t wave_sum(uint64_t v)
 {
@@ -203,28 +204,34 @@ __device__ __forceinline__ void tail_run(const KParams& P, const Work& W, const 
     const Tab B = tab_in_registers();
     const StepK K = step_k_in_registers(P);
     const Quad4 Q = quad_consts<true>(P, B);
+    // The hand-out, population and suspension checks run once per turn of kTailSteps steps (a quad whose
+    // trajectory ends early in a turn idles for the rest of it), in one loop: as a loop nested in the
+    // step loop they cost the kernel registers.
     for (;;) {
-        const uint64_t mask = __ballot(need && leader);
-        if (mask) {
-            const int first = __ffsll((unsigned long long)mask) - 1;
-            unsigned long long base = 0;
-            if (lane == first) base = atomicAdd(C.head, (unsigned long long)__popcll(mask));
-            base = __shfl(base, first, 64);
-            if (need) {
-                const int64_t slot = (int64_t)(base + __popcll(mask & lt));
-                active = slot < total;
-                if (active) {
-                    cont_load4(P, W, C, slot, k, T, i);
-                    resumed_at = T.S.nacc + T.S.nrej;
-                    resumed_rhs = T.S.nrhs;
+        if ((iters & (kTailSteps - 1)) == 0) {
+            const uint64_t mask = __ballot(need && leader);
+            if (mask) {
+                const int first = __ffsll((unsigned long long)mask) - 1;
+                unsigned long long base = 0;
+                if (lane == first) base = atomicAdd(C.head, (unsigned long long)__popcll(mask));
+                base = __shfl(base, first, 64);
+                if (need) {
+                    const int64_t slot = (int64_t)(base + __popcll(mask & lt));
+                    active = slot < total;
+                    if (active) {
+                        cont_load4(P, W, C, slot, k, T, i);
+                        resumed_at = T.S.nacc + T.S.nrej;
+                        resumed_rhs = T.S.nrhs;
+                    }
+                    need = false;
                 }
-                need = false;
             }
+            if (!__any(active)) break;
+            // every lane reads the counter in the same load, so the flag is wave-uniform
+            if (pop_limit > 0 && may_suspend && !few_left && (iters & 63) == 0)
+                few_left =
+                    total - (int64_t)__hip_atomic_load(gone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= pop_limit;
         }
-        if (!__any(active)) break;
-        // every lane reads the counter in the same load, so the flag is wave-uniform
-        if (pop_limit > 0 && may_suspend && !few_left && (iters & 63) == 0)
-            few_left = total - (int64_t)__hip_atomic_load(gone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= pop_limit;
         if (active && !T.S.done) {
             if constexpr (QUADS == 1)
                 traj4_advance_k<CE, true>(P, K, T, B);
@@ -232,6 +239,7 @@ __device__ __forceinline__ void tail_run(const KParams& P, const Work& W, const 
                 traj4_step_fast<CE>(P, K, T, B, Q);
         }
         ++iters;
+        if ((iters & (kTailSteps - 1)) != 0) continue;
         if (active && T.S.done) {
             traj4_store(W, i, T, lane & 3);
             if (leader) {
