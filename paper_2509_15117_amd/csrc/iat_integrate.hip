@@ -232,12 +232,7 @@ __device__ __forceinline__ void tail_run(const KParams& P, const Work& W, const 
                 few_left =
                     total - (int64_t)__hip_atomic_load(gone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= pop_limit;
         }
-        if (active && !T.S.done) {
-            if constexpr (QUADS == 1)
-                traj4_advance_k<CE, true>(P, K, T, B);
-            else
-                traj4_step_fast<CE>(P, K, T, B, Q);
-        }
+        if (active && !T.S.done) traj4_step_fast<CE>(P, K, T, B, Q);
         ++iters;
         if ((iters & (kTailSteps - 1)) != 0) continue;
         if (active && T.S.done) {
