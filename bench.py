@@ -49,6 +49,9 @@ def parse():
                     help="cache file of the launch-shape autotuner (stream: it always runs, on the warm-up "
                          "ids; other workloads: only with this option)")
     ap.add_argument("--no-autotune", action="store_true", help="stream: keep the default launch shape")
+    ap.add_argument("--step-budget", type=int, default=0,
+                    help=f"stream: attempted steps before a trajectory leaves the one-lane kernel (0: "
+                         f"{STREAM_STEP_BUDGET:,})")
     ap.add_argument("--graph", action="store_true",
                     help="chunked workloads (not thermal): replay one captured HIP graph per stream for the "
                          "later chunks instead of launching every chunk eagerly")
@@ -252,6 +255,10 @@ def main_chunked(args):
 
 
 STREAM_CHUNK = 1 << 22
+# step budget of the stream batch: whole batches of 20 chunks took 27.9 s at 10,000 attempted steps,
+# 27.0-27.2 s at 20,000 (the library's default), 26.7 s at 40,000 and at 80,000 (a longer one-lane
+# phase, a shorter four-lane tail)
+STREAM_STEP_BUDGET = 40000
 
 
 def main_stream(args):
@@ -273,7 +280,8 @@ def main_stream(args):
     sp = w.species()
     cur = torch.cuda.current_stream()
 
-    launch = {}
+    budget = args.step_budget if args.step_budget > 0 else STREAM_STEP_BUDGET
+    launch = {"step_budget": budget}
 
     def batch(n, id0, out, hist, **kw):
         api.integrate(w.system, sp, w.gen, n, id0=id0, out=out, counters=False, **launch, **kw)
@@ -291,7 +299,7 @@ def main_stream(args):
     if not args.no_autotune:
         # the main kernel's launch shape, timed on the warm-up range (outside the timed batch): a whole
         # chunk, so that the end of each trial launch is a small part of it, as in the batch
-        launch = api.autotune(w, n=min(C, max(id0, 1 << 16)), id0=0, cache=args.autotune or None)
+        launch = api.autotune(w, n=min(C, max(id0, 1 << 16)), id0=0, cache=args.autotune or None, step_budget=budget)
         print(f"[bench] autotuned launch {launch}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     hist = torch.zeros(len(w.gen.species) * 2 * 64 + 256, dtype=torch.float64, device=dev)
