@@ -1237,8 +1237,8 @@ __device__ __forceinline__ void traj4_advance_k(const KParams& P, const StepK& K
 // the common cases first.  When every calling quad is on an ordinary step (stepping mode, under the step
 // cap, not the final step, h above its floor) and none of them, once the step is tried, is accepted with
 // an event (periapsis inside r_b, separation floor, exit crossing, non-finite state), each quad is either
-// accepted or rejected with the plain updates of step_epilogue for those cases, chosen per lane without a
-// branch.  Otherwise every calling quad takes the general path (the same step, the same bits).
+// accepted or rejected with the plain updates of step_epilogue for those cases.  Otherwise every calling
+// quad takes the general path (the same step, the same bits).
 template <bool CE = false>
 __device__ __forceinline__ void traj4_step_fast(const KParams& P, const StepK& K, Traj4& T, const Tab& B,
                                                 const Quad4& Q)
@@ -1667,7 +1667,7 @@ __device__ __forceinline__ void traj8_advance(const KParams& P, const StepK& K, 
 // plain updates below, which are what step_prologue and step_epilogue do in these cases.  At the first
 // step that is not such a step the loop ends with the state as it was before that step, and the general
 // path takes the step again from there (same inputs, same bits); the trial's results never leave the
-// loop, so its state stays in fixed registers.  `iters` counts the attempted steps (and stops).
+// loop, so no register carries them past its exits.  `iters` counts the attempted steps (and stops).
 template <bool CE>
 __device__ __forceinline__ void traj8_run(const KParams& P, const StepK& K, Traj8& T, const Tab& B, const Oct& O,
                                           uint64_t& iters)
