@@ -157,9 +157,10 @@ def test_full_size_grid_sampled_against_oracle():
 
 @pytest.mark.parametrize("which", ["sweep_1.2e7", "stream_1e8"])
 def test_full_size_chunked_sampled_against_oracle(which):
-    """The 1.2e7 sweep and the 1e8 stream at full size, in the benchmark's launch configuration (the
-    job split over two streams, reductions on the device): 96 seeded ids copied out of their chunks
-    and checked one by one (direct) or in ensemble; the reductions count every trajectory once."""
+    """The 1.2e7 sweep (in the benchmark's launch configuration: the job split over two streams,
+    reductions on the device) and the whole 1e8 stream in the same chunked form: 96 seeded ids copied
+    out of their chunks and checked one by one (direct) or in ensemble; the reductions count every
+    trajectory once."""
     sweep = which.startswith("sweep")
     w = W.config3() if sweep else W.config5()
     n = w.n
@@ -181,6 +182,55 @@ def test_full_size_chunked_sampled_against_oracle(which):
     assert len(keep) >= 90
     sub = {k: (v[:, keep] if k == "y_final" else v[keep]) for k, v in got.items()}
     assert_parity(P[keep], ref[keep], sub, f"{w.name}-sampled", min_direct=10)
+
+
+def test_stream_batch_in_bench_configuration_sampled_against_oracle():
+    """The stream's timed batch exactly as the benchmark runs it: 20 chunks of 2^22 ids after one warm-up
+    chunk (ids 2^22 .. 21 * 2^22 - 1) in one iat_integrate call with the stream's step budget and the
+    recorded launch shape, then the on-device W0 and heating histograms.  96 seeded ids are gathered on
+    the device and checked one by one (direct) or in ensemble; the histograms and the counters count
+    every trajectory of the batch once."""
+    import bench
+    w = W.config5()
+    C = bench.STREAM_CHUNK
+    n, id0 = 20 * C, C
+    launch = dict(block=128, refill_every=16, step_budget=bench.STREAM_STEP_BUDGET)
+    dev = torch.device("cuda", 0)
+    print(f"stream batch: n={n} from id {id0}, launch {launch}, 96 sampled ids", flush=True)
+    out = api.alloc_obs(n, dev, y_final=True, counters=True)
+    stats = api.new_stats()
+    api.integrate(w.system, w.species(), w.gen, n, id0=id0, out=out, stats=stats, **launch)
+    hist = api.reduce_hist(w.system, w.species(), w.gen, n, out, id0=id0)
+    torch.cuda.synchronize()
+    hw, hh = api.split_hist(hist)
+    assert hw[..., 0].sum().item() == n and hh.sum().item() == n
+    s = stats.cpu().tolist()
+    assert s[3] == n
+    # every trajectory ends with a stop reason; every RHS evaluation and attempted step is counted once
+    ends = oracle.EXITED | oracle.TMAX | oracle.H_UNDERFLOW | oracle.NONFINITE | oracle.MAX_STEPS
+    assert int(((out["status"].to(torch.int64) & ends) == 0).sum().item()) == 0
+    na, nr = out["n_accept"].to(torch.int64), out["n_reject"].to(torch.int64)
+    assert s[1] == int(na.sum().item()) and s[5] == int((na + nr).sum().item())
+    assert s[0] == int(out["n_rhs"].to(torch.int64).sum().item())
+    del na, nr
+    longest, gid = api.longest_of(stats)
+    print(f"stream batch: longest trajectory {gid} with {longest} attempted steps; solo trajectories {s[9]}",
+          flush=True)
+    ids = np.sort(np.random.default_rng(55).choice(n, size=96, replace=False))
+    loc = torch.as_tensor(ids, device=dev)
+    got = PT.to_numpy({k: (v.index_select(1, loc) if k == "y_final" else v.index_select(0, loc))
+                       for k, v in out.items()})
+    del out
+    # as in the chunked test: the oracle stops at 2e6 accepted steps, and the few sampled complexes that
+    # live longer are left out on both sides
+    P = oracle.problems_for(w, ids + id0)
+    P["max_steps"] = 2_000_000
+    ref = oracle.integrate(P)
+    keep = np.where((got["n_accept"] < 2_000_000) & ((ref["status"] & oracle.MAX_STEPS) == 0))[0]
+    print(f"stream batch: {96 - len(keep)} sampled complexes beyond 2e6 steps left out", flush=True)
+    assert len(keep) >= 90
+    sub = {k: (v[:, keep] if k == "y_final" else v[keep]) for k, v in got.items()}
+    assert_parity(P[keep], ref[keep], sub, "stream-batch-sampled", min_direct=10)
 
 
 def _edge_system(**over):
