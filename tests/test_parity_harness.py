@@ -44,3 +44,34 @@ def test_harness_catches_a_shifted_bounce_time_and_a_wrong_lifetime_distribution
     flat["status"] = got["status"].copy()
     assert PT.survival_mismatches(ref, flat, rest)
     assert not PT.survival_mismatches(ref, got, rest)
+
+
+def test_harness_sends_a_trajectory_the_oracle_does_not_fix_to_the_ensemble(monkeypatch):
+    """A direct exit whose round-off probes spread by more than MAX_BAR / 10 is compared in ensemble
+    (its bar would exceed MAX_BAR) and counts against the few direct exits that may drop out."""
+    w = W.config1()
+    P = oracle.problems_for(w, np.arange(64))
+    ref = oracle.integrate(P)
+    got = _twin_outputs(P)
+    real = PT.classify
+    direct0, spread0, _ = real(P, ref, got)
+
+    def planted(k):
+        def cls(P_, ref_, got_, step_rates=None):
+            direct, spread, rest = real(P_, ref_, got_, step_rates)
+            spread = spread.copy()
+            spread[:k] = 2.0 * PT.MAX_BAR / 10.0
+            return direct, spread, rest
+        return cls
+
+    monkeypatch.setattr(PT, "classify", planted(1))
+    direct, rest, rep = PT.check_parity(P, ref, got, "planted-1", min_direct=10)
+    assert len(direct) == len(direct0) - 1 and direct0[0] in rest
+    assert rep["dropped_direct"] == 1 and rep["max_bar"] <= PT.MAX_BAR
+    monkeypatch.setattr(PT, "classify", planted(3))
+    try:
+        PT.check_parity(P, ref, got, "planted-3", min_direct=10)
+    except AssertionError as e:
+        assert "dropped" in str(e)
+    else:
+        raise AssertionError("three of the oracle's direct exits dropped out without failing the bar")
