@@ -635,6 +635,11 @@ __device__ __forceinline__ bool cond(bool c)
     else
         return c;
 }
+// The lanes of the wave on which one comparison holds.  ANDs and ORs of these masks are, lane by lane,
+// the masks of the ANDs and ORs of the comparisons; the ballot of a single comparison is that
+// comparison's own lane mask, while the ballot of a combined condition first turns it into a vector
+// value and back.
+__device__ __forceinline__ uint64_t lanes(bool c) { return __builtin_amdgcn_ballot_w64(c); }
 
 // Step prologue shared by both forms: picks h and handles the stops that precede a step.
 // Returns false when the trajectory stopped.
@@ -1497,7 +1502,24 @@ __device__ __forceinline__ double oct_partner(double v)
     const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x141, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
-__device__ __forceinline__ double oct_max(double v) { return quad_max(fmax(v, oct_partner(v))); }
+// max(a, b) as the one instruction, for operands that are never NaN: fmax first quiets a signalling NaN
+// in an operand that a lane move brought in, one more instruction per such operand.
+__device__ __forceinline__ double max_num(double a, double b)
+{
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+// Maximum over the octet of values that are never NaN.
+__device__ __forceinline__ double oct_max(double v)
+{
+    constexpr int x1 = 1 | (0 << 2) | (3 << 4) | (2 << 6), x2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);
+    v = max_num(v, oct_partner(v));
+    v = max_num(v, __hiloint2double(__builtin_amdgcn_mov_dpp(__double2hiint(v), x1, 0xF, 0xF, false),
+                                    __builtin_amdgcn_mov_dpp(__double2loint(v), x1, 0xF, 0xF, false)));
+    return max_num(v, __hiloint2double(__builtin_amdgcn_mov_dpp(__double2hiint(v), x2, 0xF, 0xF, false),
+                                       __builtin_amdgcn_mov_dpp(__double2loint(v), x2, 0xF, 0xF, false)));
+}
 __device__ __forceinline__ int oct_or(int v)
 {
     return quad_or(v | __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false));
@@ -1589,6 +1611,7 @@ __device__ __forceinline__ double accel8(const Lane& L, const Oct& O, double m, 
 struct Step8 {
     double x5, v5, F7, en;
     bool finite;
+    uint64_t nonfin;    // lanes(non-finite new state): 0 exactly when `finite`
     double rho_new, s_new, ww, e_prev, e_new, se_new;
 };
 template <bool CE, bool SECANT>
@@ -1609,16 +1632,18 @@ __device__ __forceinline__ Step8 traj8_trial(const KParams& P, const StepK& K, c
     R.en = 0.0;
     R.F7 = 0.0;
     R.finite = true;
+    R.nonfin = 0;
     if (!SECANT || cond<true>(!exiting)) {
         R.F7 = accel8(T.L, O, T.m, C.c6, R.x5, D);
         const double rx = err_ratio(err_x(hh, T.F1, F2, F3, F4, F5, F6, B), T.x, R.x5, K.rtol, K.atol);
         const double rv = err_ratio(err_v(h, T.F1, F3, F4, F5, F6, R.F7, B), T.v, R.v5, K.rtol, K.atol);
         // every octet of the wave holds the same trajectory: a wave ballot is the octet's OR
-        const bool bad = cond<true>(ratio_bad(rx) || ratio_bad(rv));
-        const bool nonfin = cond<true>(!(is_finite(R.x5) && is_finite(R.v5)));
+        const bool bad = (lanes(ratio_bad(rx)) | lanes(ratio_bad(rv))) != 0;
+        R.nonfin = lanes(!is_finite(R.x5)) | lanes(!is_finite(R.v5));
+        // a NaN ratio makes the step bad, and then the maximum is not used
         const double m = oct_max(fmax(rx, rv));
         R.en = bad ? __builtin_nan("") : m;
-        R.finite = !nonfin;
+        R.finite = R.nonfin == 0;
     }
     const double wk = R.v5 + oct_partner(R.v5);
     const double w0 = quad_bcast<0, true>(wk), w1 = quad_bcast<1, true>(wk), w2 = quad_bcast<2, true>(wk);
@@ -1673,23 +1698,25 @@ __device__ __forceinline__ void traj8_run(const KParams& P, const StepK& K, Traj
                                           uint64_t& iters)
 {
     Scal& S = T.S;
-    for (;;) {
-        const bool plain = (S.mode == 0) & (S.nacc < K.max_steps) & !(S.h >= K.tau_max - S.tau) & !(S.h < K.hmin);
-        if (!cond<true>(plain)) break;
+    // the loop never changes the mode: stepping mode is tested once
+    for (bool stepping = lanes(S.mode == 0) != 0; stepping;) {
+        const uint64_t plain =
+            lanes(S.nacc < K.max_steps) & lanes(!(S.h >= K.tau_max - S.tau)) & lanes(!(S.h < K.hmin));
+        if (plain == 0) break;
         const double h = S.h;
         const Step8 R = traj8_trial<CE, false>(P, K, T, B, O, h, false);
-        const bool acc = R.en <= 1.0;
+        const uint64_t acc = lanes(R.en <= 1.0);
         const double ex_prev = CE ? R.e_prev : S.rho_prev, ex_new = CE ? R.e_new : R.rho_new;
-        // bitwise, not short-circuit, so that no condition becomes a branch of its own
-        const bool bounce =
-            (S.s_prev < 0.0) & (R.s_new >= 0.0) & (fmin(S.rho_prev, R.rho_new) < T.L.rm2 * K.rb_ratio2);
-        const bool floor = R.rho_new < 0.01 * T.L.rm2;
-        const bool crossing = (ex_prev <= K.r0sq) & (ex_new > K.r0sq) & ((CE ? R.se_new : R.s_new) > 0.0);
-        const bool event = acc & (!R.finite | bounce | floor | crossing);
-        if (cond<true>(event)) break;
+        const uint64_t bounce = lanes(S.s_prev < 0.0) & lanes(R.s_new >= 0.0) &
+                                lanes(fmin(S.rho_prev, R.rho_new) < T.L.rm2 * K.rb_ratio2);
+        const uint64_t floor = lanes(R.rho_new < 0.01 * T.L.rm2);
+        const uint64_t crossing =
+            lanes(ex_prev <= K.r0sq) & lanes(ex_new > K.r0sq) & lanes((CE ? R.se_new : R.s_new) > 0.0);
+        const uint64_t event = acc & (R.nonfin | bounce | floor | crossing);
+        if (event != 0) break;
         ++iters;
         S.nrhs += 6;
-        if (cond<true>(acc)) {
+        if (acc != 0) {
             S.nacc++;
             S.status |= bound_state(T.L, R.rho_new, R.ww) ? (uint32_t)IAT_ST_BOUND_SEEN : 0u;
             S.tau = S.tau + h;
