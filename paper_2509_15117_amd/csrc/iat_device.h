@@ -1529,7 +1529,7 @@ __device__ __forceinline__ int oct_or(int v)
 struct Oct {
     bool atom;        // lanes 0..3: the atom's side of the half-row mirror
     bool l0;          // lane 0: evaluates the series of the phase remainder
-    double kA, qr;    // this lane's axis k: a_k / 4 and q_k / q_x
+    double kA, qr;    // ion lanes, axis k: a_k / 4 and q_k / q_x; +0 on atom lanes
     double cl;        // lanes 1..5: the offset coefficient c2, c3, c4, c5, 1 of this lane's stage series
 };
 __device__ __forceinline__ Oct oct_consts(const KParams& P, const Tab& T)
@@ -1538,8 +1538,9 @@ __device__ __forceinline__ Oct oct_consts(const KParams& P, const Tab& T)
     Oct O;
     O.atom = l < 4;
     O.l0 = l == 0;
-    O.kA = ax == 0 ? P.kA[0] : (ax == 1 ? P.kA[1] : P.kA[2]);
-    O.qr = ax == 0 ? P.q_ratio[0] : (ax == 1 ? P.q_ratio[1] : P.q_ratio[2]);
+    // the trap acts on the ion only: +0 on the atom's lanes (then K = kA + qc qr is +0 there)
+    O.kA = O.atom ? 0.0 : (ax == 0 ? P.kA[0] : (ax == 1 ? P.kA[1] : P.kA[2]));
+    O.qr = O.atom ? 0.0 : (ax == 0 ? P.q_ratio[0] : (ax == 1 ? P.q_ratio[1] : P.q_ratio[2]));
     O.cl = l == 1 ? T.c2 : (l == 2 ? T.c3 : (l == 3 ? T.c4 : (l == 4 ? T.c5 : 1.0)));
     // opaque values: the compiler keeps them in registers instead of re-deriving them per step
     asm volatile("" : "+v"(O.kA), "+v"(O.qr), "+v"(O.cl));
@@ -1590,14 +1591,17 @@ __device__ __forceinline__ Sep8 sep8(double X)
 // and acc_ion in one expression: with t = s d_k and m = 1/m_a (atom lanes) or 1/m_i (ion lanes),
 //   atom:  (s d_k) / m_a                  = fma(t, m, -0)        (adding -0 leaves every product as is)
 //   ion:   -acc_ion = -fma(-t, m, K X)    = fma(t, m, -(K X))    (X = -x_ion; rounding is sign-symmetric)
-// where K = kA + qc qr and K X is rounded as the product K x_ion of the other forms.
+// where K = kA + qc qr and K X is rounded as the product K x_ion of the other forms.  The addend is
+// fma(K, X, +0) on every lane: the rounded product K X when that is not zero, and +0 when it is, so on the
+// atom lanes (K = +0) it is the -0 of the atom's expression.  On an ion lane an exactly zero K X thus
+// enters as -0 where the other forms add +0, which changes the result only when t m is an exact -0 as
+// well: the sign of an exactly zero acceleration.
 __device__ __forceinline__ double accel8(const Lane& L, const Oct& O, double m, double cs, double X, const Sep8& D)
 {
     const double s = force_scale_rr(L, D.rr);
     const double qc = L.qx_half * cs;
-    const double kx = (O.kA + qc * O.qr) * X;
-    const double c = O.atom ? 0.0 : kx;
-    return fma(s * D.dk, m, -c);
+    const double kx = fma(O.kA + qc * O.qr, X, 0.0);
+    return fma(s * D.dk, m, -kx);
 }
 __device__ __forceinline__ double accel8(const Lane& L, const Oct& O, double m, double cs, double X)
 {
