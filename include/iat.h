@@ -312,6 +312,25 @@ int iat_adjoint(const iat_system* sys, const iat_species* species, int n_species
 int iat_adjoint_workspace_bytes(const iat_system* sys, const iat_species* species, int n_species,
                                 const iat_batch* batch, const iat_obs* obs, size_t* bytes, void* stream);
 
+/* Device workspace of one call, for callers that budget device memory before it (the integration,
+ * reduction and adjoint of the batched trajectories above; the calls themselves allocate and free
+ * what they need, stream-ordered, unless a workspace is passed in).  which:
+ *   IAT_WS_INTEGRATE  bytes iat_integrate allocates for this batch and launch (launch may be NULL:
+ *                     defaults): 256 B of counters, the work buffer (196 B per trajectory) and the
+ *                     continuation records of the tail and solo levels (248 B each); host only;
+ *   IAT_WS_REDUCE     bytes iat_reduce of kind reduce_kind allocates for this batch (CELLS: partial
+ *                     sums per cell and slice; BOXCOUNT: level flags; the histogram kinds: 0); host only;
+ *   IAT_WS_ADJOINT    as iat_adjoint_workspace_bytes (reads obs of the forward run on `stream` and
+ *                     synchronises it).
+ * obs and stream are used by IAT_WS_ADJOINT only, reduce_kind by IAT_WS_REDUCE only.  Writes *bytes
+ * (host); returns the validation errors of the call it sizes, IAT_EINVAL for an unknown `which`. */
+#define IAT_WS_INTEGRATE 1
+#define IAT_WS_REDUCE 2
+#define IAT_WS_ADJOINT 3
+int iat_workspace_bytes(int which, const iat_system* sys, const iat_species* species, int n_species,
+                        const iat_batch* batch, const iat_obs* obs, const iat_launch* launch, int reduce_kind,
+                        size_t* bytes, void* stream);
+
 /* Diagnostics: the FP64 rate this GPU sustains on independent FMAs (eight chains per lane,
  * n_threads lanes, a multiple of 256, `iters` x 64 FMAs each), timed with HIP events on the
  * stream; writes TFLOP/s to *tflops (host).  scratch: device double[n_threads] (written).  The

@@ -20,7 +20,8 @@ REDUCE_CELLS, REDUCE_W0_HIST, REDUCE_BOXCOUNT, REDUCE_LIFETIME, REDUCE_W0_HIST_B
 W0_BINS, HEAT_BINS, LIFE_BINS, LIFE_SLOT = 64, 256, 96, 98
 
 EXPORTS = ["iat_integrate", "iat_integrate_noalloc", "iat_integrate_tangent", "iat_adjoint", "iat_reduce", "iat_adjoint_workspace_bytes",
-           "iat_fp64_peak", "iat_last_error", "iat_version", "iat_release"]
+           "iat_workspace_bytes", "iat_fp64_peak", "iat_last_error", "iat_version", "iat_release"]
+WS_INTEGRATE, WS_REDUCE, WS_ADJOINT = 1, 2, 3
 
 _d = ctypes.c_double
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -98,6 +99,9 @@ def load():
     L.iat_adjoint_workspace_bytes.argtypes = [_P(System), _P(Species), ctypes.c_int, _P(Batch), _P(Obs),
                                               _P(ctypes.c_size_t), _vp]
     L.iat_adjoint_workspace_bytes.restype = ctypes.c_int
+    L.iat_workspace_bytes.argtypes = [ctypes.c_int, _P(System), _P(Species), ctypes.c_int, _P(Batch), _P(Obs),
+                                      _P(Launch), ctypes.c_int, _P(ctypes.c_size_t), _vp]
+    L.iat_workspace_bytes.restype = ctypes.c_int
     L.iat_fp64_peak.argtypes = [_vp, ctypes.c_int64, ctypes.c_int, _P(ctypes.c_double), _vp]
     L.iat_fp64_peak.restype = ctypes.c_int
     L.iat_last_error.restype = ctypes.c_char_p

@@ -337,6 +337,29 @@ def adjoint_workspace_bytes(system, species, gen, n: int, obs, *, arrays=None, i
     return int(out.value)
 
 
+def workspace_bytes(which: str, system, species, gen, n: int, *, arrays=None, id0=None, reduce_kind="w0_hist",
+                    obs=None, stream=None, **launch) -> int:
+    """Device bytes that one call over ids [id0, id0 + n) needs: which = 'integrate' (what iat_integrate
+    allocates for this launch shape; launch keyword arguments as for integrate()), 'reduce' (what
+    iat_reduce of reduce_kind allocates: 'cells', 'w0_hist', 'w0_hist_bound', 'boxcount', 'lifetime')
+    or 'adjoint' (as adjoint_workspace_bytes; needs obs of the forward run)."""
+    kinds = {"integrate": _abi.WS_INTEGRATE, "reduce": _abi.WS_REDUCE, "adjoint": _abi.WS_ADJOINT}
+    reduces = {"cells": _abi.REDUCE_CELLS, "w0_hist": _abi.REDUCE_W0_HIST, "w0_hist_bound": _abi.REDUCE_W0_HIST_BOUND,
+               "boxcount": _abi.REDUCE_BOXCOUNT, "lifetime": _abi.REDUCE_LIFETIME}
+    L = _abi.load()
+    sysv = system_struct(system)
+    sp = species_array(species)
+    b = batch_struct(n, gen, arrays, None, id0)
+    o = obs_struct(obs) if obs is not None else None
+    la = launch_struct(**launch)
+    out = ctypes.c_size_t(0)
+    rc = L.iat_workspace_bytes(kinds[which], ctypes.byref(sysv), sp, len(species), ctypes.byref(b),
+                               ctypes.byref(o) if o is not None else None, ctypes.byref(la), reduces[reduce_kind],
+                               ctypes.byref(out), _stream_handle(stream) if which == "adjoint" else None)
+    _abi.check(rc)
+    return int(out.value)
+
+
 class ScatteringObservables(torch.autograd.Function):
     """obs = (angle, q_transfer, dE_ion) per trajectory as a differentiable function of per-trajectory
     (theta, phi, E, q_x, De) tensors (float64, device, length n); the backward pass is the library's

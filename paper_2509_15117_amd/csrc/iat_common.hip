@@ -256,3 +256,23 @@ int resolve_launch(const iat_launch* launch, iat_launch* out)
 }
 
 }  // namespace iat
+
+extern "C" int iat_workspace_bytes(int which, const iat_system* sys, const iat_species* species, int n_species,
+                                   const iat_batch* batch, const iat_obs* obs, const iat_launch* launch,
+                                   int reduce_kind, size_t* bytes, void* stream)
+{
+    using namespace iat;
+    if (!bytes) return set_error(IAT_EINVAL, "bytes is NULL");
+    switch (which) {
+    case IAT_WS_INTEGRATE:
+        return integrate_ws_bytes(sys, species, n_species, batch, launch, bytes);
+    case IAT_WS_REDUCE: {
+        const int rc = validate_common(sys, species, n_species, batch);
+        return rc ? rc : reduce_ws_bytes(batch, reduce_kind, bytes);
+    }
+    case IAT_WS_ADJOINT:
+        return iat_adjoint_workspace_bytes(sys, species, n_species, batch, obs, bytes, stream);
+    default:
+        return set_error(IAT_EINVAL, "unknown workspace kind %d", which);
+    }
+}

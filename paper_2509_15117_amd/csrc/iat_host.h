@@ -18,6 +18,10 @@ int resolve_launch(const iat_launch* launch, iat_launch* out);
 // setup (ids -> start states, lane constants) and observables kernels over a work buffer
 void launch_setup(const KParams& P, const Work& W, hipStream_t st);
 void launch_observe(const KParams& P, const Work& W, hipStream_t st);
+// device bytes that iat_integrate and iat_reduce allocate for a batch (host only, nothing launched)
+int integrate_ws_bytes(const iat_system* sys, const iat_species* species, int n_species, const iat_batch* batch,
+                       const iat_launch* launch, size_t* bytes);
+int reduce_ws_bytes(const iat_batch* batch, int kind, size_t* bytes);
 
 // HIP-event timing of a call's phases into a host float[kMarks - 1] (no-op when out is NULL).
 class PhaseTimer {

@@ -402,14 +402,15 @@ struct IntegrateCall {
     bool ce = false;
 };
 
+// sizing: only the workspace is wanted (obs may be NULL, nothing is launched)
 static int integrate_prepare(const iat_system* sys, const iat_species* species, int n_species,
                              const iat_batch* batch, const iat_obs* obs, const iat_launch* launch,
-                             int64_t suspended_limit, int64_t solo_limit, IntegrateCall& c)
+                             int64_t suspended_limit, int64_t solo_limit, IntegrateCall& c, bool sizing = false)
 {
     int rc = validate_common(sys, species, n_species, batch);
     if (rc) return rc;
-    if (!obs) return set_error(IAT_EINVAL, "obs is NULL");
-    if (batch->n > 0 &&
+    if (!obs && !sizing) return set_error(IAT_EINVAL, "obs is NULL");
+    if (obs && batch->n > 0 &&
         (!obs->angle || !obs->q_transfer || !obs->dE_ion || !obs->t_dwell || !obs->n_bounce || !obs->status))
         return set_error(IAT_EINVAL, "obs: angle, q_transfer, dE_ion, t_dwell, n_bounce and status are required");
     rc = resolve_launch(launch, &c.L);
@@ -417,7 +418,7 @@ static int integrate_prepare(const iat_system* sys, const iat_species* species, 
     c.n = batch->n;
     if (c.n > (int64_t)0x7fffffff * 256) return set_error(IAT_EINVAL, "batch too large for one launch");
     fill_params(c.P, sys, species, n_species, batch);
-    fill_outputs(c.P, obs);
+    if (obs) fill_outputs(c.P, obs);
     c.P.stats = c.L.stats;
     c.P.refill_every = c.L.refill_every;
     c.P.budget = 0;
@@ -551,6 +552,16 @@ static int scratch_address(void** out)
         addr[dev] = p;
     }
     *out = addr[dev];
+    return 0;
+}
+
+int integrate_ws_bytes(const iat_system* sys, const iat_species* species, int n_species, const iat_batch* batch,
+                       const iat_launch* launch, size_t* bytes)
+{
+    IntegrateCall c;
+    const int rc = integrate_prepare(sys, species, n_species, batch, nullptr, launch, kMaxSuspended, kMaxSolo, c, true);
+    if (rc) return rc;
+    *bytes = c.n == 0 ? 0 : workspace_bytes(c.n, c.cap, c.cap2);
     return 0;
 }
 

@@ -263,6 +263,45 @@ __global__ void k_boxcount_fit(const unsigned long long* counts, int levels, int
 
 }  // namespace iat
 
+namespace iat {
+
+// Device bytes of the CELLS partial sums (per cell and slice: count, complexes and three sums).
+static size_t cells_part_bytes(int64_t ncell) { return (size_t)ncell * kSlices * 5 * sizeof(double); }
+static int64_t n_cells(const iat_gen& g)
+{
+    return (int64_t)g.n_species * (g.n_E > 0 ? g.n_E : 1) * (g.n_q > 0 ? g.n_q : 1) * (g.n_De > 0 ? g.n_De : 1);
+}
+// BOXCOUNT buffer: level counters, then one flag byte per cell of the current level and of the next.
+static void box_layout(int64_t n, size_t& cbytes, size_t& fbytes, size_t& gbytes)
+{
+    cbytes = 256;
+    fbytes = (size_t)n;
+    gbytes = (size_t)n / 4 + 1;
+}
+
+int reduce_ws_bytes(const iat_batch* batch, int kind, size_t* bytes)
+{
+    size_t c = 0, f = 0, g = 0;
+    switch (kind) {
+    case IAT_REDUCE_CELLS:
+        *bytes = batch->n == 0 ? 0 : cells_part_bytes(n_cells(batch->gen));
+        return 0;
+    case IAT_REDUCE_BOXCOUNT:
+        box_layout(batch->n, c, f, g);
+        *bytes = batch->n == 0 ? 0 : c + f + g;
+        return 0;
+    case IAT_REDUCE_W0_HIST:
+    case IAT_REDUCE_W0_HIST_BOUND:
+    case IAT_REDUCE_LIFETIME:
+        *bytes = 0;          // these accumulate straight into `out`
+        return 0;
+    default:
+        return set_error(IAT_EINVAL, "unknown reduce kind %d", kind);
+    }
+}
+
+}  // namespace iat
+
 using namespace iat;
 
 extern "C" int iat_reduce(const iat_system* sys, const iat_species* species, int n_species, const iat_batch* batch,
@@ -282,11 +321,9 @@ extern "C" int iat_reduce(const iat_system* sys, const iat_species* species, int
     if (kind == IAT_REDUCE_CELLS) {
         if (batch->gen.kind != IAT_GEN_SWEEP && batch->gen.kind != IAT_GEN_THERMAL)
             return set_error(IAT_EINVAL, "reduce CELLS needs a SWEEP or THERMAL batch");
-        const iat_gen& g = batch->gen;
-        const int64_t ncell = (int64_t)g.n_species * (g.n_E > 0 ? g.n_E : 1) * (g.n_q > 0 ? g.n_q : 1) *
-                              (g.n_De > 0 ? g.n_De : 1);
+        const int64_t ncell = n_cells(batch->gen);
         void* part = nullptr;
-        const size_t bytes = (size_t)ncell * kSlices * 5 * sizeof(double);
+        const size_t bytes = cells_part_bytes(ncell);
         if (hipMallocAsync(&part, bytes, st) != hipSuccess) return set_error(IAT_EHIP, "hipMallocAsync failed");
         const int64_t threads = ncell * kSlices;
         hipLaunchKernelGGL(k_reduce_cells, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, P, R,
@@ -315,8 +352,8 @@ extern "C" int iat_reduce(const iat_system* sys, const iat_species* species, int
             return set_error(IAT_EINVAL, "reduce BOXCOUNT needs a square power-of-two grid, side 2..32768");
         int levels = 0;
         while ((1 << levels) <= nt) ++levels;
-        // counters | level flags (n bytes) | next level flags (n/4 bytes)
-        const size_t cbytes = 256, fbytes = (size_t)batch->n, gbytes = (size_t)batch->n / 4 + 1;
+        size_t cbytes, fbytes, gbytes;
+        box_layout(batch->n, cbytes, fbytes, gbytes);
         void* buf = nullptr;
         if (hipMallocAsync(&buf, cbytes + fbytes + gbytes, st) != hipSuccess)
             return set_error(IAT_EHIP, "hipMallocAsync failed");

@@ -211,3 +211,44 @@ def test_run_chunks_refuses_graph_replay_of_thermal_batches_without_gpu():
         api.run_chunks(W.fig3_thermal(), n=64, chunk=32, graph=True, cells=True)
     with pytest.raises(ValueError, match="samples"):
         api.run_chunks(W.config3(), n=64, chunk=32, graph=True, sample=[1, 2])
+
+
+def test_workspace_bytes_of_integrate_and_reduce_on_the_host():
+    """iat_workspace_bytes sizes the calls without a GPU: iat_integrate's workspace is 256 B of counters,
+    the work buffer (22 doubles and 5 ints per trajectory, rounded up to 256 B) and 248 B per
+    continuation record of the tail and solo levels (one of each per trajectory for small batches; none
+    for the plain kernel or without a step budget); iat_reduce allocates per-cell partial sums for
+    CELLS (64 slices of 5 doubles), level flags for BOXCOUNT and nothing for the histograms."""
+    from paper_2509_15117_amd import api
+    w = W.config1()
+    sysv, sp = w.system, w.species()
+
+    def ws(which, wl=w, n=64, **kw):
+        return api.workspace_bytes(which, wl.system, wl.species(), wl.gen, n, **kw)
+
+    def ceil256(x):
+        return -(-x // 256) * 256
+    s3 = W.config3()
+    for n in (1, 64, 1000):
+        work = 256 + ceil256(n * (22 * 8 + 5 * 4))
+        assert ws("integrate", wl=s3, n=n) == work + 2 * n * 248
+        assert ws("integrate", wl=s3, n=n, kernel="plain") == work
+        assert ws("integrate", wl=s3, n=n, step_budget=-1) == work
+        assert ws("integrate", wl=s3, n=n, max_suspended=5) == work + 2 * min(n, 5) * 248
+    assert ws("integrate", n=0) == 0
+    with pytest.raises(_abi.IatError, match="exceed"):        # the call's own validation: 1000 ids of an 8x8 grid
+        ws("integrate", n=1000)
+    assert ws("reduce", wl=s3, n=1000, reduce_kind="cells") == 225 * 64 * 5 * 8
+    for k in ("w0_hist", "w0_hist_bound", "lifetime"):
+        assert ws("reduce", n=64, reduce_kind=k) == 0
+    assert ws("reduce", n=64, reduce_kind="boxcount") == 256 + 64 + 64 // 4 + 1
+    L = _abi.load()
+    b = api.batch_struct(64, w.gen)
+    out = ctypes.c_size_t(7)
+    args = (ctypes.byref(api.system_struct(sysv)), api.species_array(sp), 1, ctypes.byref(b), None,
+            ctypes.byref(_abi.Launch()))
+    assert L.iat_workspace_bytes(9, *args, 0, ctypes.byref(out), None) == _abi.IAT_EINVAL
+    assert b"unknown workspace kind" in L.iat_last_error()
+    assert L.iat_workspace_bytes(_abi.WS_REDUCE, *args, 99, ctypes.byref(out), None) == _abi.IAT_EINVAL
+    assert L.iat_workspace_bytes(_abi.WS_INTEGRATE, *args, 0, None, None) == _abi.IAT_EINVAL
+    assert out.value == 7
