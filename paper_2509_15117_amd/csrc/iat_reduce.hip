@@ -38,7 +38,7 @@ constexpr int kLifeBins = 96, kLifeSlot = kLifeBins + 2;     // + censored count
 constexpr double kLifeLo = -2.0, kLifeHi = 4.0;
 constexpr double kAuTimeMicro = 2.4188843265857e-11;           // atomic unit of time in microseconds
 
-__device__ __forceinline__ int64_t cell_count(const iat_gen& g)
+__host__ __device__ __forceinline__ int64_t cell_count(const iat_gen& g)
 {
     const int64_t nE = g.n_E > 0 ? g.n_E : 1, nq = g.n_q > 0 ? g.n_q : 1, nD = g.n_De > 0 ? g.n_De : 1;
     return (int64_t)g.n_species * nE * nq * nD;
@@ -267,10 +267,6 @@ namespace iat {
 
 // Device bytes of the CELLS partial sums (per cell and slice: count, complexes and three sums).
 static size_t cells_part_bytes(int64_t ncell) { return (size_t)ncell * kSlices * 5 * sizeof(double); }
-static int64_t n_cells(const iat_gen& g)
-{
-    return (int64_t)g.n_species * (g.n_E > 0 ? g.n_E : 1) * (g.n_q > 0 ? g.n_q : 1) * (g.n_De > 0 ? g.n_De : 1);
-}
 // BOXCOUNT buffer: level counters, then one flag byte per cell of the current level and of the next.
 static void box_layout(int64_t n, size_t& cbytes, size_t& fbytes, size_t& gbytes)
 {
@@ -279,12 +275,32 @@ static void box_layout(int64_t n, size_t& cbytes, size_t& fbytes, size_t& gbytes
     gbytes = (size_t)n / 4 + 1;
 }
 
+// The batch conditions of the reductions that need them (EINVAL otherwise).
+static int reduce_check(const iat_batch* batch, int kind)
+{
+    const iat_gen& g = batch->gen;
+    if (kind == IAT_REDUCE_CELLS && g.kind != IAT_GEN_SWEEP && g.kind != IAT_GEN_THERMAL)
+        return set_error(IAT_EINVAL, "reduce CELLS needs a SWEEP or THERMAL batch");
+    if (kind == IAT_REDUCE_BOXCOUNT) {
+        if (g.kind != IAT_GEN_GRID || g.id0 != 0 || batch->id0_dev || batch->n != (int64_t)g.n_theta * g.n_phi)
+            return set_error(IAT_EINVAL, "reduce BOXCOUNT needs a whole GRID batch");
+        const int nt = g.n_theta;
+        if (nt != g.n_phi || nt < 2 || (nt & (nt - 1)) != 0 || nt > 32768)
+            return set_error(IAT_EINVAL, "reduce BOXCOUNT needs a square power-of-two grid, side 2..32768");
+    }
+    return 0;
+}
+
 int reduce_ws_bytes(const iat_batch* batch, int kind, size_t* bytes)
 {
     size_t c = 0, f = 0, g = 0;
+    if (batch->n > 0) {
+        const int rc = reduce_check(batch, kind);
+        if (rc) return rc;
+    }
     switch (kind) {
     case IAT_REDUCE_CELLS:
-        *bytes = batch->n == 0 ? 0 : cells_part_bytes(n_cells(batch->gen));
+        *bytes = batch->n == 0 ? 0 : cells_part_bytes(cell_count(batch->gen));
         return 0;
     case IAT_REDUCE_BOXCOUNT:
         box_layout(batch->n, c, f, g);
@@ -318,10 +334,10 @@ extern "C" int iat_reduce(const iat_system* sys, const iat_species* species, int
             obs->t_bounce_first, obs->t_bounce_last};
     hipStream_t st = (hipStream_t)stream;
     if (batch->n == 0) return 0;
+    rc = reduce_check(batch, kind);
+    if (rc) return rc;
     if (kind == IAT_REDUCE_CELLS) {
-        if (batch->gen.kind != IAT_GEN_SWEEP && batch->gen.kind != IAT_GEN_THERMAL)
-            return set_error(IAT_EINVAL, "reduce CELLS needs a SWEEP or THERMAL batch");
-        const int64_t ncell = n_cells(batch->gen);
+        const int64_t ncell = cell_count(batch->gen);
         void* part = nullptr;
         const size_t bytes = cells_part_bytes(ncell);
         if (hipMallocAsync(&part, bytes, st) != hipSuccess) return set_error(IAT_EHIP, "hipMallocAsync failed");
@@ -345,11 +361,7 @@ extern "C" int iat_reduce(const iat_system* sys, const iat_species* species, int
         hipLaunchKernelGGL(k_life_fit, dim3(1), dim3(64), 0, st, out, nsp);
     } else if (kind == IAT_REDUCE_BOXCOUNT) {
         const iat_gen& g = batch->gen;
-        if (g.kind != IAT_GEN_GRID || g.id0 != 0 || batch->id0_dev || batch->n != (int64_t)g.n_theta * g.n_phi)
-            return set_error(IAT_EINVAL, "reduce BOXCOUNT needs a whole GRID batch");
-        const int nt = g.n_theta, npp = g.n_phi;
-        if (nt != npp || nt < 2 || (nt & (nt - 1)) != 0 || nt > 32768)
-            return set_error(IAT_EINVAL, "reduce BOXCOUNT needs a square power-of-two grid, side 2..32768");
+        const int nt = g.n_theta;
         int levels = 0;
         while ((1 << levels) <= nt) ++levels;
         size_t cbytes, fbytes, gbytes;

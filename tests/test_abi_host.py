@@ -252,3 +252,16 @@ def test_workspace_bytes_of_integrate_and_reduce_on_the_host():
     assert L.iat_workspace_bytes(_abi.WS_REDUCE, *args, 99, ctypes.byref(out), None) == _abi.IAT_EINVAL
     assert L.iat_workspace_bytes(_abi.WS_INTEGRATE, *args, 0, None, None) == _abi.IAT_EINVAL
     assert out.value == 7
+
+
+def test_workspace_bytes_refuses_what_the_reduction_refuses():
+    from paper_2509_15117_amd import api
+    g = W.config1()
+    with pytest.raises(_abi.IatError, match="CELLS needs a SWEEP"):
+        api.workspace_bytes("reduce", g.system, g.species(), g.gen, 64, reduce_kind="cells")
+    with pytest.raises(_abi.IatError, match="whole GRID"):
+        api.workspace_bytes("reduce", g.system, g.species(), g.gen, 32, reduce_kind="boxcount")
+    s3 = W.config3()
+    with pytest.raises(_abi.IatError, match="whole GRID"):
+        api.workspace_bytes("reduce", s3.system, s3.species(), s3.gen, 64, reduce_kind="boxcount")
+    assert api.workspace_bytes("reduce", g.system, g.species(), g.gen, 0, reduce_kind="cells") == 0
