@@ -155,16 +155,17 @@ def test_full_size_grid_sampled_against_oracle():
     assert_parity(P, ref, sub, "config2-sampled", min_direct=10)
 
 
-@pytest.mark.parametrize("which", ["sweep_1.2e7", "stream_1e8"])
+@pytest.mark.parametrize("which", ["sweep_1.2e7", "stream_1e8", "fig4_5e6"])
 def test_full_size_chunked_sampled_against_oracle(which):
-    """The 1.2e7 sweep (in the benchmark's launch configuration: the job split over two streams,
-    reductions on the device) and the whole 1e8 stream in the same chunked form: 96 seeded ids copied
-    out of their chunks and checked one by one (direct) or in ensemble; the reductions count every
-    trajectory once."""
+    """The 1.2e7 sweep and the 5e6 Fig. 4 energy sweep (r0 = 20,000 a0) in the benchmark's launch
+    configuration (the job split over two streams, reductions on the device), and the whole 1e8 stream
+    in the same chunked form: 96 seeded ids copied out of their chunks and checked one by one (direct)
+    or in ensemble; the reductions count every trajectory once."""
     sweep = which.startswith("sweep")
-    w = W.config3() if sweep else W.config5()
+    w = {"sweep_1.2e7": W.config3, "stream_1e8": W.config5, "fig4_5e6": W.fig4_energy}[which]()
     n = w.n
-    ids = np.sort(np.random.default_rng(3 if sweep else 5).choice(n, size=96, replace=False))
+    seed = {"sweep_1.2e7": 3, "stream_1e8": 5, "fig4_5e6": 44}[which]
+    ids = np.sort(np.random.default_rng(seed).choice(n, size=96, replace=False))
     print(f"{w.name}: n={n} in two chunks on two streams, 96 sampled ids", flush=True)
     res = api.run_chunks(w, n=n, chunk=-(-n // 2), n_streams=2, cells=sweep, hist=not sweep, sample=ids)
     got = PT.to_numpy(res["sample"])
@@ -172,7 +173,7 @@ def test_full_size_chunked_sampled_against_oracle(which):
         assert res["cells"][:, 0].sum().item() == n
     else:
         assert api.split_hist(res["hist"])[1].sum().item() == n
-    # the oracle stops at 2e6 accepted steps (the library runs to its default cap of 2e7): the few
+    # the oracle stops at 2e6 accepted steps (the library runs to the workloads' cap of 2e7): the few
     # sampled complexes that live longer are left out on both sides
     P = oracle.problems_for(w, ids)
     P["max_steps"] = 2_000_000
